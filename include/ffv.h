@@ -1,0 +1,157 @@
+/*
+ * ffv.h — C ABI of the MI355X view-interpolation library (libffv.so).
+ *
+ * The library evaluates the forward pass of the view-interpolation network of
+ * "A Multi-user Oriented Live Free-viewpoint Video Streaming System Based On
+ * View Interpolation" (section 3.1, Eq. 1 and Eq. 2; supplementary layer
+ * table): given two neighbouring camera images it synthesises the virtual
+ * view at phase t between them. Every step runs in the library's own HIP
+ * kernels for gfx950.
+ *
+ * Conventions for every entry point:
+ *   - Each call returns an ffv_status; nothing throws or aborts across the
+ *     ABI. On failure ffv_last_error() describes the cause.
+ *   - Image pointers are DEVICE pointers to planar float32 [3][H][W] RGB in
+ *     [0, 1], contiguous, owned by the caller.
+ *   - The library owns the net, its packed weights, its workspace, resident
+ *     camera data and tickets.
+ */
+#ifndef FFV_H
+#define FFV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FFV_ABI_VERSION 1
+
+typedef struct ffv_net ffv_net; /* opaque, library-owned */
+
+typedef enum {
+  FFV_OK = 0,
+  FFV_PENDING = 1,       /* request admitted or queued, not finished */
+  FFV_ERR_ARG = -1,      /* invalid argument (null, size, t out of [0,1], NaN) */
+  FFV_ERR_OOM = -2,      /* device allocation failed */
+  FFV_ERR_BUDGET = -3,   /* request can never fit the admission budget */
+  FFV_ERR_DEVICE = -4,   /* HIP runtime error (launch, copy, sync) */
+  FFV_ERR_WEIGHTS = -5,  /* weights file missing, malformed, checksum or shape mismatch */
+  FFV_ERR_TICKET = -6,   /* unknown or already collected ticket */
+  FFV_ERR_STATE = -7     /* call not valid in the net's current state */
+} ffv_status;
+
+typedef enum {
+  FFV_FP32 = 0,      /* convolutions on fp32 MFMA, fp32 activations */
+  FFV_BF16 = 1,      /* convolutions on bf16 MFMA with fp32 accumulation */
+  FFV_FP8_E4M3 = 2   /* reserved: fp8 e4m3 convolutions (not built) */
+} ffv_precision;
+
+typedef struct {
+  int32_t abi_version;          /* must be FFV_ABI_VERSION */
+  int32_t precision;            /* ffv_precision */
+  int32_t device;               /* HIP device ordinal */
+  int32_t reserved0;
+  void* stream;                 /* hipStream_t to order against; NULL = library stream */
+  uint64_t workspace_bytes;     /* cap on the per-call workspace; 0 = 16 GiB */
+  uint64_t hbm_budget_bytes;    /* serving admission budget; 0 = serving off */
+  float tick_ms;                /* serving tick; <= 0 means 5 ms */
+  int32_t max_batch_views;      /* views per launch in serving; 0 = 64 */
+} ffv_opts;
+
+/* Fills *opts with the defaults (FP32, device 0, library stream, 16 GiB
+ * workspace cap, serving off). */
+void ffv_default_opts(ffv_opts* opts);
+
+/*
+ * Load a .ffvw weights file (layout: magic "FFVW", version 1, text header
+ * with base width, t-plane flag and per-layer shapes/offsets, SHA-256 of the
+ * float32 payload) and build a net for opts->precision on opts->device.
+ * Weights are checked against the network definition (section 3.1 and the
+ * supplementary layer table) and packed for the chosen precision.
+ * Errors: FFV_ERR_ARG (null args, ABI version), FFV_ERR_WEIGHTS (file),
+ * FFV_ERR_DEVICE / FFV_ERR_OOM (device).
+ */
+ffv_status ffv_create_net(const char* weights_path, const ffv_opts* opts, ffv_net** out);
+
+/* Release everything the net owns. Waits for its in-flight work. NULL is a no-op. */
+void ffv_destroy_net(ffv_net* net);
+
+typedef struct {
+  const float* left;   /* device, planar [3][H][W] float32 */
+  const float* right;  /* device, planar [3][H][W] float32 */
+  int32_t height, width;
+} ffv_pair;
+
+/*
+ * Synthesise n_t virtual views for each of n_pairs camera pairs: the view at
+ * phase t[j] between pair i's left (t = 0) and right (t = 1) image, per the
+ * network of section 3.1 (Eq. 1, Eq. 2). All pairs share one height and
+ * width (>= 2 each). Pairs that share an image pointer share its per-camera
+ * work (image pyramid, context features).
+ *   t:   HOST array of n_t phases, each in [0, 1].
+ *   out: DEVICE float32 [n_pairs][n_t][3][H][W], caller-owned.
+ * Work is ordered on opts->stream (or the library stream); the call returns
+ * after the output is written. Not thread-safe per net.
+ * Errors: FFV_ERR_ARG (nulls, n <= 0, mixed sizes, t outside [0,1] or NaN),
+ * FFV_ERR_OOM, FFV_ERR_DEVICE.
+ */
+ffv_status ffv_interpolate(ffv_net* net, const ffv_pair* views, int32_t n_pairs,
+                           const float* t, int32_t n_t, float* out);
+
+/* Last error message of the calling thread (valid until its next call). */
+const char* ffv_last_error(void);
+
+/* ---------------------------------------------------------------------- */
+/* Instrumentation (used by tests and the benchmark)                       */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * Copy an intermediate tensor of view 0 of the last ffv_interpolate call to
+ * the DEVICE buffer dst as float32 [C][Hs][Ws] (C, Hs, Ws written to dims).
+ * Names: "F0" "F1" "F2" (flow+mask, 5 channels, stage resolution),
+ * "I2" (blended view, 3 channels, padded size).
+ * Only available when the net was created with debug taps enabled
+ * (ffv_set_debug). Errors: FFV_ERR_ARG (unknown name, capacity too small),
+ * FFV_ERR_STATE (no taps recorded).
+ */
+ffv_status ffv_debug_tap(ffv_net* net, const char* name, float* dst, size_t capacity_floats,
+                         int32_t dims[3]);
+ffv_status ffv_set_debug(ffv_net* net, int32_t enable);
+
+/*
+ * Per-kernel-class timing with HIP events recorded on the work stream.
+ * ffv_set_profiling(net, 1) clears and starts collection; ffv_kernel_stats
+ * returns, for the class named `name`, the number of launches, the summed
+ * device time in milliseconds and the summed algorithmic work (flops for
+ * convolution classes, bytes for per-pixel classes). Class names:
+ * "conv256" (3x3 stride-1 convs with 256 in/out channels), "conv" (other
+ * convolutions), "convT" (transposed convs), "pixel" (warp/resample/blend
+ * passes), "head" (output head).
+ */
+ffv_status ffv_set_profiling(ffv_net* net, int32_t enable);
+ffv_status ffv_kernel_stats(ffv_net* net, const char* name, int64_t* launches, double* ms,
+                            double* work);
+
+/*
+ * One convolution layer through the library's implicit-GEMM kernel (kernel
+ * unit tests). 3x3 conv, padding 1, stride 1 or 2 (transposed = 0), or 4x4
+ * stride-2 padding-1 transposed conv (transposed = 1); optional ReLU.
+ *   x:      DEVICE float32 planar [n][cin][h][w]
+ *   weight: HOST float32, [cout][cin][3][3] (conv) or [cin][cout][4][4] (transposed)
+ *   bias:   HOST float32 [cout]
+ *   y:      DEVICE float32 planar [n][cout][ho][wo], ho = (h-1)/stride+1
+ *           (conv) or 2h (transposed)
+ * precision: FFV_FP32 or FFV_BF16 (inputs and weights rounded to bf16, fp32
+ * accumulation and output). Allocates temporaries; synchronises `stream`.
+ */
+ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, int32_t cin, int32_t h,
+                       int32_t w, const float* weight, const float* bias, int32_t cout,
+                       int32_t stride, int32_t transposed, int32_t relu, float* y, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFV_H */

@@ -1,0 +1,217 @@
+// extern "C" entry points of libffv.so (declared in include/ffv.h).
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+
+#include "../../include/ffv.h"
+#include "net.h"
+
+struct ffv_net {
+  ffv::Net net;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ffv_status fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return (ffv_status)code;
+}
+
+ffv_status from(const ffv::Status& s) {
+  if (s.good()) {
+    g_last_error.clear();
+    return FFV_OK;
+  }
+  return fail(s.code, s.msg);
+}
+
+}  // namespace
+
+extern "C" {
+
+void ffv_default_opts(ffv_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->abi_version = FFV_ABI_VERSION;
+  o->precision = FFV_FP32;
+  o->device = 0;
+  o->stream = nullptr;
+  o->workspace_bytes = 0;
+  o->hbm_budget_bytes = 0;
+  o->tick_ms = 5.0f;
+  o->max_batch_views = 0;
+}
+
+ffv_status ffv_create_net(const char* weights_path, const ffv_opts* opts, ffv_net** out) {
+  if (!weights_path || !opts || !out) return fail(FFV_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (opts->abi_version != FFV_ABI_VERSION) return fail(FFV_ERR_ARG, "ABI version mismatch");
+  if (opts->precision == FFV_FP8_E4M3) return fail(FFV_ERR_ARG, "FP8 precision is not built");
+  if (opts->precision != FFV_FP32 && opts->precision != FFV_BF16)
+    return fail(FFV_ERR_ARG, "unknown precision");
+  try {
+    ffv_net* n = new ffv_net();
+    ffv::Status s = n->net.init(weights_path, opts->precision, opts->device,
+                                (hipStream_t)opts->stream, opts->workspace_bytes);
+    if (!s.good()) {
+      delete n;
+      return from(s);
+    }
+    *out = n;
+    g_last_error.clear();
+    return FFV_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(FFV_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(FFV_ERR_DEVICE, e.what());
+  }
+}
+
+void ffv_destroy_net(ffv_net* net) { delete net; }
+
+ffv_status ffv_interpolate(ffv_net* net, const ffv_pair* views, int32_t n_pairs, const float* t,
+                           int32_t n_t, float* out) {
+  if (!net || !views || !t || !out) return fail(FFV_ERR_ARG, "null argument");
+  if (n_pairs <= 0 || n_t <= 0) return fail(FFV_ERR_ARG, "n_pairs and n_t must be positive");
+  const int H = views[0].height, W = views[0].width;
+  if (H < 2 || W < 2) return fail(FFV_ERR_ARG, "height and width must be >= 2");
+  if ((long)H * W > (1L << 28)) return fail(FFV_ERR_ARG, "image too large");
+  for (int i = 0; i < n_pairs; ++i) {
+    if (!views[i].left || !views[i].right) return fail(FFV_ERR_ARG, "null image pointer");
+    if (views[i].height != H || views[i].width != W)
+      return fail(FFV_ERR_ARG, "all pairs of one call must share height and width");
+  }
+  for (int j = 0; j < n_t; ++j)
+    if (!(t[j] >= 0.f && t[j] <= 1.f)) return fail(FFV_ERR_ARG, "t must lie in [0, 1]");
+  try {
+    std::vector<const float*> l(n_pairs), r(n_pairs);
+    for (int i = 0; i < n_pairs; ++i) {
+      l[i] = views[i].left;
+      r[i] = views[i].right;
+    }
+    return from(net->net.interpolate(l.data(), r.data(), n_pairs, H, W, t, n_t, out));
+  } catch (const std::bad_alloc&) {
+    return fail(FFV_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(FFV_ERR_DEVICE, e.what());
+  }
+}
+
+const char* ffv_last_error(void) { return g_last_error.c_str(); }
+
+ffv_status ffv_debug_tap(ffv_net* net, const char* name, float* dst, size_t capacity_floats,
+                         int32_t dims[3]) {
+  if (!net || !name || !dst || !dims) return fail(FFV_ERR_ARG, "null argument");
+  int d[3] = {0, 0, 0};
+  ffv_status st = from(net->net.debug_tap(name, dst, capacity_floats, d));
+  dims[0] = d[0];
+  dims[1] = d[1];
+  dims[2] = d[2];
+  return st;
+}
+
+ffv_status ffv_set_debug(ffv_net* net, int32_t enable) {
+  if (!net) return fail(FFV_ERR_ARG, "null net");
+  net->net.set_debug(enable != 0);
+  return FFV_OK;
+}
+
+ffv_status ffv_set_profiling(ffv_net* net, int32_t enable) {
+  if (!net) return fail(FFV_ERR_ARG, "null net");
+  net->net.set_profiling(enable != 0);
+  return FFV_OK;
+}
+
+ffv_status ffv_kernel_stats(ffv_net* net, const char* name, int64_t* launches, double* ms,
+                            double* work) {
+  if (!net || !name || !launches || !ms || !work) return fail(FFV_ERR_ARG, "null argument");
+  long l = 0;
+  ffv_status st = from(net->net.kernel_stats(name, &l, ms, work));
+  *launches = l;
+  return st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Operator-level entry point (kernel unit tests).
+extern "C" ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, int32_t cin,
+                                  int32_t h, int32_t w, const float* weight, const float* bias,
+                                  int32_t cout, int32_t stride, int32_t transposed, int32_t relu,
+                                  float* y, void* stream) {
+  using namespace ffv;
+  if (!x || !weight || !bias || !y) return fail(FFV_ERR_ARG, "null argument");
+  if (precision != FFV_FP32 && precision != FFV_BF16) return fail(FFV_ERR_ARG, "precision");
+  if (n <= 0 || cin <= 0 || h <= 0 || w <= 0 || cout <= 0) return fail(FFV_ERR_ARG, "sizes");
+  if (!transposed && stride != 1 && stride != 2) return fail(FFV_ERR_ARG, "stride");
+  const DType dt = precision == FFV_FP32 ? DType::F32 : DType::BF16;
+  hipStream_t s = (hipStream_t)stream;
+  Layer L;
+  L.transposed = transposed != 0;
+  L.cin = cin;
+  L.cout = cout;
+  L.stride = L.transposed ? 2 : stride;
+  const size_t nw = (size_t)cin * cout * (L.transposed ? 16 : 9);
+  L.w_host.assign(weight, weight + nw);
+  L.b_host.assign(bias, bias + cout);
+  plan_layer(L);
+  const int ho = L.transposed ? 2 * h : (h - 1) / stride + 1;
+  const int wo = L.transposed ? 2 * w : (w - 1) / stride + 1;
+  std::vector<uint8_t> packed = pack_layer(L, dt);
+  const size_t e = dtype_size(dt);
+  void *xin = nullptr, *wd = nullptr, *bd = nullptr, *yo = nullptr;
+  auto cleanup = [&]() {
+    if (xin) hipFree(xin);
+    if (wd) hipFree(wd);
+    if (bd) hipFree(bd);
+    if (yo) hipFree(yo);
+  };
+  hipError_t err = hipMalloc(&xin, (size_t)n * h * w * L.cin_pad * e);
+  if (err == hipSuccess) err = hipMalloc(&wd, packed.size());
+  if (err == hipSuccess) err = hipMalloc(&bd, (size_t)cout * 4);
+  if (err == hipSuccess) err = hipMalloc(&yo, (size_t)n * ho * wo * cout * 4);
+  if (err == hipSuccess) err = hipMemcpy(wd, packed.data(), packed.size(), hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = hipMemcpy(bd, bias, (size_t)cout * 4, hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = launch_pack_nhwc(x, n, cin, h, w, xin, L.cin_pad, dt, s);
+  if (err == hipSuccess) {
+    ConvArgs a{};
+    a.in = xin;
+    a.in_img_stride = (long)h * w * L.cin_pad;
+    a.in_ld = L.cin_pad;
+    a.Hi = h;
+    a.Wi = w;
+    a.wgt = wd;
+    a.bias = (const float*)bd;
+    a.out = yo;
+    a.out_img_stride = (long)ho * wo * cout;
+    a.out_ld = cout;
+    a.Ho = L.transposed ? h : ho;
+    a.Wo = L.transposed ? w : wo;
+    a.Hout = ho;
+    a.Wout = wo;
+    a.cin_pad = L.cin_pad;
+    a.K = L.K;
+    a.K_pad = L.K_pad;
+    a.cout = cout;
+    a.cout_pad = L.cout_pad;
+    a.n_img = n;
+    a.stride = L.transposed ? 1 : stride;
+    a.transposed = L.transposed ? 1 : 0;
+    a.relu = relu ? 1 : 0;
+    a.out_f32 = 1;
+    a.accumulate = 0;
+    err = launch_conv(dt, L.tile, a, s);
+  }
+  for (int i = 0; err == hipSuccess && i < n; ++i)
+    err = launch_extract((const float*)yo + (size_t)i * ho * wo * cout, DType::F32, cout, cout,
+                         (long)ho * wo, y + (size_t)i * cout * ho * wo, s);
+  if (err == hipSuccess) err = hipStreamSynchronize(s);
+  cleanup();
+  if (err != hipSuccess) return fail(FFV_ERR_DEVICE, hipGetErrorString(err));
+  g_last_error.clear();
+  return FFV_OK;
+}

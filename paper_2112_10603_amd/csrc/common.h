@@ -1,0 +1,96 @@
+// Shared declarations of the HIP library: element types, kernel argument
+// structs and the host-side launchers implemented in the .hip files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ffv {
+
+typedef __bf16 bf16;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+enum class DType : int { F32 = 0, BF16 = 1 };
+
+inline size_t dtype_size(DType t) { return t == DType::F32 ? 4 : 2; }
+
+// One implicit-GEMM convolution launch: C[m][n] = sum_k A[m][k] * B[n][k].
+//   m: output pixel of the GEMM grid (image, oy, ox), M = n_img * Ho * Wo
+//   n: output channel
+//   k: (tap, input channel); taps are the 9 offsets of a 3x3 conv, or the 4
+//      taps of one output phase of a 4x4 stride-2 transposed conv
+// Activations are NHWC with a pixel stride (ld) that may exceed the channel
+// count, so a layer can read or write a channel slice of a wider buffer.
+struct ConvArgs {
+  const void* in;       // input base, already offset to the first channel
+  long in_img_stride;   // elements between images
+  int in_ld;            // elements between pixels
+  int Hi, Wi;           // input size
+  const void* wgt;      // packed weights [phase][Cout_pad][K_pad], act dtype
+  const float* bias;    // [Cout]
+  void* out;            // output base, already offset to the first channel
+  long out_img_stride;
+  int out_ld;
+  int Ho, Wo;           // GEMM grid size (transposed: = input size)
+  int Hout, Wout;       // output image size (transposed: 2x the grid)
+  int cin_pad;          // input channels, multiple of 8 (zero weights past the real count)
+  int K;                // taps * cin_pad
+  int K_pad;            // K rounded up to the K tile
+  int cout;             // real output channels
+  int cout_pad;         // rows per phase in the packed weights
+  int n_img;
+  int stride;           // 1 or 2 (conv); 1 for transposed
+  int transposed;       // 0: 3x3 conv, 1: 4x4 s2 transposed (blockIdx.z = phase)
+  int relu;
+  int out_f32;          // 1: float output, 0: activation dtype
+  int accumulate;       // 1: add into the existing float output
+};
+
+// Tile shapes the conv kernel is instantiated for.
+enum class ConvTile : int { M128_N128 = 0, M128_N64 = 1, M128_N32 = 2 };
+
+hipError_t launch_conv(DType dt, ConvTile tile, const ConvArgs& a, hipStream_t s);
+
+// Per-view description for per-pixel kernels.
+struct ViewDesc {
+  int cam_l, cam_r;  // camera slots
+  float t;           // phase
+  int pad;
+};
+
+// Per-camera resident data (all NHWC).
+struct CamPtrs {
+  const float* X4;  // padded image, 4 floats per pixel (RGB, 0), Hp x Wp
+  const float* L0;  // quarter size, 4 floats per pixel
+  const float* L1;  // half size
+};
+
+hipError_t launch_ingest(const float* const* src, int n_cam, int H, int W, int Hp, int Wp,
+                         float* X4, void* Xa, DType dt, hipStream_t s);
+hipError_t launch_resample4(const float* in, int n_img, int Hi, int Wi, float* out, int Ho, int Wo,
+                            hipStream_t s);
+hipError_t launch_assemble0(const ViewDesc* views, int n_views, const float* L0, long cam_stride,
+                            int h, int w, void* x, int ld, DType dt, int t_plane, hipStream_t s);
+hipError_t launch_transition(const ViewDesc* views, int n_views, const float* FMprev, int hp, int wp,
+                             const float* Limg, long cam_stride, int h, int w, void* x, int ld,
+                             float* FM, DType dt, int t_plane, hipStream_t s);
+hipError_t launch_final(const ViewDesc* views, int n_views, const float* FM, const float* X4,
+                        long cam_stride, int h, int w, float* I2, void* x0u, int ld, DType dt,
+                        hipStream_t s);
+hipError_t launch_flow_down(const float* in, int in_ld, int n_img, int h, int w, float* out,
+                            hipStream_t s);
+hipError_t launch_ctx_warp(const ViewDesc* views, int n_views, const void* feat, long cam_stride,
+                           int C, const float* flow, int h, int w, void* dst, int dst_ld,
+                           long dst_img_stride, DType dt, hipStream_t s);
+hipError_t launch_head(const void* u4, int ld, int C, const float* w, const float* b,
+                       const float* I2, int n_img, int Hp, int Wp, int H, int W, float* out,
+                       DType dt, hipStream_t s);
+hipError_t launch_extract(const void* src, DType dt, int ld, int C, long n_pix, float* dst,
+                          hipStream_t s);
+hipError_t launch_pack_nhwc(const float* src, int n_img, int C, int H, int W, void* dst, int ld,
+                            DType dt, hipStream_t s);
+
+}  // namespace ffv

@@ -1,0 +1,463 @@
+// Per-pixel passes of the view-interpolation network: ingest and padding,
+// the image pyramid, stage input assembly with flow upscaling and backward
+// warps (Eq. 2), the final warp and mask blend (Eq. 1), the flow pyramid and
+// the context-feature warps of the refinement U-Net, and the output head.
+//
+// All are memory-bound: one thread per output pixel (or per 8-channel group
+// of a pixel), NHWC so the threads of a wavefront touch consecutive pixels.
+// Sample positions, bilinear weights, flows and the mask stay fp32 in every
+// precision; only the activations fed to convolutions use the activation
+// dtype.
+#include "common.h"
+
+namespace ffv {
+
+namespace {
+
+constexpr int TPB = 256;
+
+template <typename T>
+__device__ inline T cvt(float v) {
+  return (T)v;
+}
+
+__device__ inline float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+
+// Half-pixel-centre source coordinate for resampling n_in -> n_out.
+__device__ inline void hp_tap(int i, int n_in, int n_out, int& i0, int& i1, float& w) {
+  float s = ((float)i + 0.5f) * ((float)n_in / (float)n_out) - 0.5f;
+  s = fmaxf(s, 0.f);
+  int f = (int)floorf(s);
+  if (f > n_in - 1) f = n_in - 1;
+  i0 = f;
+  i1 = min(f + 1, n_in - 1);
+  w = s - (float)f;
+}
+
+// Backward bilinear sample position u + f, clamped to the image (border mode).
+struct Tap4 {
+  int o00, o01, o10, o11;  // pixel offsets
+  float w00, w01, w10, w11;
+};
+
+__device__ inline Tap4 warp_taps(int x, int y, float fx, float fy, int w, int h) {
+  float px = fminf(fmaxf((float)x + fx, 0.f), (float)(w - 1));
+  float py = fminf(fmaxf((float)y + fy, 0.f), (float)(h - 1));
+  int x0 = (int)floorf(px), y0 = (int)floorf(py);
+  int x1 = min(x0 + 1, w - 1), y1 = min(y0 + 1, h - 1);
+  float a = px - (float)x0, b = py - (float)y0;
+  Tap4 t;
+  t.o00 = y0 * w + x0;
+  t.o01 = y0 * w + x1;
+  t.o10 = y1 * w + x0;
+  t.o11 = y1 * w + x1;
+  t.w00 = (1.f - a) * (1.f - b);
+  t.w01 = a * (1.f - b);
+  t.w10 = (1.f - a) * b;
+  t.w11 = a * b;
+  return t;
+}
+
+__device__ inline float4 sample4(const float* img, const Tap4& t) {
+  float4 p00 = ld4(img + 4L * t.o00), p01 = ld4(img + 4L * t.o01);
+  float4 p10 = ld4(img + 4L * t.o10), p11 = ld4(img + 4L * t.o11);
+  float4 r;
+  r.x = t.w00 * p00.x + t.w01 * p01.x + t.w10 * p10.x + t.w11 * p11.x;
+  r.y = t.w00 * p00.y + t.w01 * p01.y + t.w10 * p10.y + t.w11 * p11.y;
+  r.z = t.w00 * p00.z + t.w01 * p01.z + t.w10 * p10.z + t.w11 * p11.z;
+  r.w = 0.f;
+  return r;
+}
+
+// ---------------------------------------------------------------- ingest
+template <typename T>
+__global__ void ingest_k(const float* const* src, int H, int W, int Hp, int Wp, float* X4, T* Xa) {
+  const int cam = blockIdx.y;
+  const long P = (long)Hp * Wp;
+  const long p = (long)blockIdx.x * TPB + threadIdx.x;
+  if (p >= P) return;
+  const int y = (int)(p / Wp), x = (int)(p % Wp);
+  const int sy = min(y, H - 1), sx = min(x, W - 1);
+  const float* s = src[cam];
+  const long HW = (long)H * W;
+  const float r = s[(long)sy * W + sx], g = s[HW + (long)sy * W + sx], b = s[2 * HW + (long)sy * W + sx];
+  *reinterpret_cast<float4*>(X4 + (cam * P + p) * 4) = make_float4(r, g, b, 0.f);
+  T* xa = Xa + (cam * P + p) * 8;
+  xa[0] = cvt<T>(r);
+  xa[1] = cvt<T>(g);
+  xa[2] = cvt<T>(b);
+#pragma unroll
+  for (int c = 3; c < 8; ++c) xa[c] = cvt<T>(0.f);
+}
+
+// ----------------------------------------------------- 4-channel resample
+__global__ void resample4_k(const float* in, int Hi, int Wi, float* out, int Ho, int Wo) {
+  const int img = blockIdx.y;
+  const long p = (long)blockIdx.x * TPB + threadIdx.x;
+  if (p >= (long)Ho * Wo) return;
+  const int y = (int)(p / Wo), x = (int)(p % Wo);
+  int y0, y1, x0, x1;
+  float by, ax;
+  hp_tap(y, Hi, Ho, y0, y1, by);
+  hp_tap(x, Wi, Wo, x0, x1, ax);
+  const float* b = in + (long)img * Hi * Wi * 4;
+  float4 a00 = ld4(b + 4L * (y0 * Wi + x0)), a01 = ld4(b + 4L * (y0 * Wi + x1));
+  float4 a10 = ld4(b + 4L * (y1 * Wi + x0)), a11 = ld4(b + 4L * (y1 * Wi + x1));
+  float4 r;
+  r.x = (a00.x * (1.f - ax) + a01.x * ax) * (1.f - by) + (a10.x * (1.f - ax) + a11.x * ax) * by;
+  r.y = (a00.y * (1.f - ax) + a01.y * ax) * (1.f - by) + (a10.y * (1.f - ax) + a11.y * ax) * by;
+  r.z = (a00.z * (1.f - ax) + a01.z * ax) * (1.f - by) + (a10.z * (1.f - ax) + a11.z * ax) * by;
+  r.w = (a00.w * (1.f - ax) + a01.w * ax) * (1.f - by) + (a10.w * (1.f - ax) + a11.w * ax) * by;
+  *reinterpret_cast<float4*>(out + ((long)img * Ho * Wo + p) * 4) = r;
+}
+
+// ------------------------------------------------------ stage-0 input
+template <typename T>
+__global__ void assemble0_k(const ViewDesc* views, const float* L0, long cam_stride, int h, int w,
+                            T* x, int ld, int t_plane) {
+  const int v = blockIdx.y;
+  const long P = (long)h * w;
+  const long p = (long)blockIdx.x * TPB + threadIdx.x;
+  if (p >= P) return;
+  const ViewDesc d = views[v];
+  const float4 l = ld4(L0 + d.cam_l * cam_stride + 4 * p);
+  const float4 r = ld4(L0 + d.cam_r * cam_stride + 4 * p);
+  T* o = x + ((long)v * P + p) * ld;
+  o[0] = cvt<T>(l.x);
+  o[1] = cvt<T>(l.y);
+  o[2] = cvt<T>(l.z);
+  o[3] = cvt<T>(r.x);
+  o[4] = cvt<T>(r.y);
+  o[5] = cvt<T>(r.z);
+  o[6] = cvt<T>(t_plane ? d.t : 0.f);
+  for (int c = 7; c < ld; ++c) o[c] = cvt<T>(0.f);
+}
+
+// ---------------------------------------- stage transition s -> s+1 (Eq. 2)
+// FM layout: 8 floats per pixel = (F_l.x, F_l.y, F_r.x, F_r.y, M, 0, 0, 0).
+template <typename T>
+__global__ void transition_k(const ViewDesc* views, const float* FMprev, int hp, int wp,
+                             const float* Limg, long cam_stride, int h, int w, T* x, int ld,
+                             float* FM, int t_plane) {
+  const int v = blockIdx.y;
+  const long P = (long)h * w;
+  const long p = (long)blockIdx.x * TPB + threadIdx.x;
+  if (p >= P) return;
+  const ViewDesc d = views[v];
+  const int y = (int)(p / w), xx = (int)(p % w);
+  int y0, y1, x0, x1;
+  float by, ax;
+  hp_tap(y, hp, h, y0, y1, by);
+  hp_tap(xx, wp, w, x0, x1, ax);
+  const float* fp = FMprev + (long)v * hp * wp * 8;
+  const float* q00 = fp + 8L * (y0 * wp + x0);
+  const float* q01 = fp + 8L * (y0 * wp + x1);
+  const float* q10 = fp + 8L * (y1 * wp + x0);
+  const float* q11 = fp + 8L * (y1 * wp + x1);
+  float up[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c)
+    up[c] = (q00[c] * (1.f - ax) + q01[c] * ax) * (1.f - by) + (q10[c] * (1.f - ax) + q11[c] * ax) * by;
+  const float Fx = 2.f * up[0], Fy = 2.f * up[1], Gx = 2.f * up[2], Gy = 2.f * up[3], Mt = up[4];
+
+  const float* Lc = Limg + d.cam_l * cam_stride;
+  const float* Rc = Limg + d.cam_r * cam_stride;
+  const float4 L = ld4(Lc + 4 * p), R = ld4(Rc + 4 * p);
+  const float4 Wl = sample4(Lc, warp_taps(xx, y, Fx, Fy, w, h));
+  const float4 Wr = sample4(Rc, warp_taps(xx, y, Gx, Gy, w, h));
+
+  T* o = x + ((long)v * P + p) * ld;
+  const float vals[18] = {L.x, L.y, L.z, R.x, R.y, R.z, Wl.x, Wl.y, Wl.z, Wr.x, Wr.y, Wr.z,
+                          Mt, Fx, Fy, Gx, Gy, t_plane ? d.t : 0.f};
+#pragma unroll
+  for (int c = 0; c < 18; ++c) o[c] = cvt<T>(vals[c]);
+  for (int c = 18; c < ld; ++c) o[c] = cvt<T>(0.f);
+  float* f = FM + ((long)v * P + p) * 8;
+  *reinterpret_cast<float4*>(f) = make_float4(Fx, Fy, Gx, Gy);
+  *reinterpret_cast<float4*>(f + 4) = make_float4(Mt, 0.f, 0.f, 0.f);
+}
+
+// ------------------------------------ final warp + mask blend (Eq. 1)
+template <typename T>
+__global__ void final_k(const ViewDesc* views, const float* FM, const float* X4, long cam_stride,
+                        int h, int w, float* I2, T* x0u, int ld) {
+  const int v = blockIdx.y;
+  const long P = (long)h * w;
+  const long p = (long)blockIdx.x * TPB + threadIdx.x;
+  if (p >= P) return;
+  const ViewDesc d = views[v];
+  const int y = (int)(p / w), xx = (int)(p % w);
+  const float* f = FM + ((long)v * P + p) * 8;
+  const float4 F = ld4(f);
+  const float M = f[4];
+  const float* Lc = X4 + d.cam_l * cam_stride;
+  const float* Rc = X4 + d.cam_r * cam_stride;
+  const float4 L = ld4(Lc + 4 * p), R = ld4(Rc + 4 * p);
+  const float4 Wl = sample4(Lc, warp_taps(xx, y, F.x, F.y, w, h));
+  const float4 Wr = sample4(Rc, warp_taps(xx, y, F.z, F.w, w, h));
+  const float m = 1.f / (1.f + expf(-M));
+  float4 o;
+  o.x = m * Wl.x + (1.f - m) * Wr.x;
+  o.y = m * Wl.y + (1.f - m) * Wr.y;
+  o.z = m * Wl.z + (1.f - m) * Wr.z;
+  o.w = 0.f;
+  *reinterpret_cast<float4*>(I2 + ((long)v * P + p) * 4) = o;
+  T* u = x0u + ((long)v * P + p) * ld;
+  const float vals[17] = {L.x, L.y, L.z, R.x, R.y, R.z, Wl.x, Wl.y, Wl.z,
+                          Wr.x, Wr.y, Wr.z, M, F.x, F.y, F.z, F.w};
+#pragma unroll
+  for (int c = 0; c < 17; ++c) u[c] = cvt<T>(vals[c]);
+  for (int c = 17; c < ld; ++c) u[c] = cvt<T>(0.f);
+}
+
+// -------------------------------------------- flow pyramid: F/2 of 2x2 mean
+__global__ void flow_down_k(const float* in, int in_ld, int h, int w, float* out) {
+  const int img = blockIdx.y;
+  const int ho = h / 2, wo = w / 2;
+  const long p = (long)blockIdx.x * TPB + threadIdx.x;
+  if (p >= (long)ho * wo) return;
+  const int y = (int)(p / wo), x = (int)(p % wo);
+  const float* b = in + (long)img * h * w * in_ld;
+  const float4 a = ld4(b + (long)in_ld * ((2 * y) * w + 2 * x));
+  const float4 c = ld4(b + (long)in_ld * ((2 * y) * w + 2 * x + 1));
+  const float4 e = ld4(b + (long)in_ld * ((2 * y + 1) * w + 2 * x));
+  const float4 g = ld4(b + (long)in_ld * ((2 * y + 1) * w + 2 * x + 1));
+  float4 r;
+  r.x = 0.5f * (0.5f * (0.5f * (a.x + c.x) + 0.5f * (e.x + g.x)));
+  r.y = 0.5f * (0.5f * (0.5f * (a.y + c.y) + 0.5f * (e.y + g.y)));
+  r.z = 0.5f * (0.5f * (0.5f * (a.z + c.z) + 0.5f * (e.z + g.z)));
+  r.w = 0.5f * (0.5f * (0.5f * (a.w + c.w) + 0.5f * (e.w + g.w)));
+  *reinterpret_cast<float4*>(out + ((long)img * ho * wo + p) * 4) = r;
+}
+
+// ------------------------------------------------ context-feature warp
+// One thread per (pixel, 8-channel group); groups [0, C/8) warp the left
+// camera's features by F_l, groups [C/8, C/4) the right's by F_r.
+template <typename T>
+__global__ void ctx_warp_k(const ViewDesc* views, const T* feat, long cam_stride, int C,
+                           const float* flow, int h, int w, T* dst, int dst_ld, long dst_img_stride) {
+  const int v = blockIdx.y;
+  const int G = C / 4;  // groups for both sides
+  const long P = (long)h * w;
+  const long id = (long)blockIdx.x * TPB + threadIdx.x;
+  if (id >= P * G) return;
+  const long p = id / G;
+  const int g = (int)(id - p * G);
+  const bool right = g >= G / 2;
+  const int c0 = (right ? g - G / 2 : g) * 8;
+  const ViewDesc d = views[v];
+  const int y = (int)(p / w), x = (int)(p % w);
+  const float4 F = ld4(flow + ((long)v * P + p) * 4);
+  const Tap4 t = right ? warp_taps(x, y, F.z, F.w, w, h) : warp_taps(x, y, F.x, F.y, w, h);
+  const T* src = feat + (right ? d.cam_r : d.cam_l) * cam_stride + c0;
+  float acc[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) acc[i] = 0.f;
+  const int offs[4] = {t.o00, t.o01, t.o10, t.o11};
+  const float ws[4] = {t.w00, t.w01, t.w10, t.w11};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const T* s = src + (long)offs[q] * C;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] += ws[q] * (float)s[i];
+  }
+  T* o = dst + (long)v * dst_img_stride + p * dst_ld + (right ? C : 0) + c0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) o[i] = cvt<T>(acc[i]);
+}
+
+// ----------------------------------------------------------- output head
+// r = sigmoid(conv3x3(u4 -> 3)); out = clamp(I2 + 2r - 1, 0, 1), cropped and
+// written planar [3][H][W]. C (the U-Net's last width) is at most 64.
+template <typename T>
+__global__ void head_k(const T* u4, int ld, int C, const float* wgt, const float* bias,
+                       const float* I2, int Hp, int Wp, int H, int W, float* out) {
+  __shared__ float ws[3 * 64 * 9 + 3];
+  const int nw = 3 * C * 9;
+  for (int i = threadIdx.x; i < nw; i += TPB) ws[i] = wgt[i];
+  if (threadIdx.x < 3) ws[nw + threadIdx.x] = bias[threadIdx.x];
+  __syncthreads();
+  const int v = blockIdx.y;
+  const long p = (long)blockIdx.x * TPB + threadIdx.x;
+  if (p >= (long)H * W) return;
+  const int y = (int)(p / W), x = (int)(p % W);
+  const T* base = u4 + (long)v * Hp * Wp * ld;
+  float z0 = ws[nw], z1 = ws[nw + 1], z2 = ws[nw + 2];
+  for (int dy = 0; dy < 3; ++dy) {
+    const int yy = y + dy - 1;
+    if (yy < 0 || yy >= Hp) continue;
+    for (int dx = 0; dx < 3; ++dx) {
+      const int xx = x + dx - 1;
+      if (xx < 0 || xx >= Wp) continue;
+      const T* s = base + ((long)yy * Wp + xx) * ld;
+      const int tap = dy * 3 + dx;
+      for (int c = 0; c < C; ++c) {
+        const float a = (float)s[c];
+        z0 += ws[(0 * C + c) * 9 + tap] * a;
+        z1 += ws[(1 * C + c) * 9 + tap] * a;
+        z2 += ws[(2 * C + c) * 9 + tap] * a;
+      }
+    }
+  }
+  const float4 b = ld4(I2 + ((long)v * Hp * Wp + (long)y * Wp + x) * 4);
+  const float r0 = 1.f / (1.f + expf(-z0)), r1 = 1.f / (1.f + expf(-z1)), r2 = 1.f / (1.f + expf(-z2));
+  const long HW = (long)H * W;
+  float* o = out + (long)v * 3 * HW;
+  o[p] = fminf(fmaxf(b.x + 2.f * r0 - 1.f, 0.f), 1.f);
+  o[HW + p] = fminf(fmaxf(b.y + 2.f * r1 - 1.f, 0.f), 1.f);
+  o[2 * HW + p] = fminf(fmaxf(b.z + 2.f * r2 - 1.f, 0.f), 1.f);
+}
+
+// -------------------------------------------------------- layout helpers
+template <typename T>
+__global__ void extract_k(const T* src, int ld, int C, long n_pix, float* dst) {
+  const long p = (long)blockIdx.x * TPB + threadIdx.x;
+  if (p >= n_pix) return;
+  for (int c = 0; c < C; ++c) dst[c * n_pix + p] = (float)src[p * ld + c];
+}
+
+template <typename T>
+__global__ void pack_nhwc_k(const float* src, int C, int H, int W, T* dst, int ld) {
+  const int img = blockIdx.y;
+  const long P = (long)H * W;
+  const long p = (long)blockIdx.x * TPB + threadIdx.x;
+  if (p >= P) return;
+  const float* s = src + (long)img * C * P;
+  T* o = dst + ((long)img * P + p) * ld;
+  for (int c = 0; c < ld; ++c) o[c] = cvt<T>(c < C ? s[c * P + p] : 0.f);
+}
+
+inline dim3 grid1(long n, int y) { return dim3((unsigned)((n + TPB - 1) / TPB), (unsigned)y); }
+
+}  // namespace
+
+#define FFV_DISPATCH(dt, KERNEL, ...)                                     \
+  do {                                                                     \
+    if ((dt) == DType::F32)                                                \
+      hipLaunchKernelGGL(KERNEL<float>, __VA_ARGS__);                      \
+    else                                                                   \
+      hipLaunchKernelGGL(KERNEL<bf16>, __VA_ARGS__);                       \
+  } while (0)
+
+hipError_t launch_ingest(const float* const* src, int n_cam, int H, int W, int Hp, int Wp, float* X4,
+                         void* Xa, DType dt, hipStream_t s) {
+  if (n_cam <= 0) return hipSuccess;
+  if (dt == DType::F32)
+    hipLaunchKernelGGL(ingest_k<float>, grid1((long)Hp * Wp, n_cam), dim3(TPB), 0, s, src, H, W, Hp,
+                       Wp, X4, (float*)Xa);
+  else
+    hipLaunchKernelGGL(ingest_k<bf16>, grid1((long)Hp * Wp, n_cam), dim3(TPB), 0, s, src, H, W, Hp,
+                       Wp, X4, (bf16*)Xa);
+  return hipGetLastError();
+}
+
+hipError_t launch_resample4(const float* in, int n_img, int Hi, int Wi, float* out, int Ho, int Wo,
+                            hipStream_t s) {
+  if (n_img <= 0) return hipSuccess;
+  hipLaunchKernelGGL(resample4_k, grid1((long)Ho * Wo, n_img), dim3(TPB), 0, s, in, Hi, Wi, out, Ho,
+                     Wo);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble0(const ViewDesc* views, int n_views, const float* L0, long cam_stride,
+                            int h, int w, void* x, int ld, DType dt, int t_plane, hipStream_t s) {
+  if (n_views <= 0) return hipSuccess;
+  if (dt == DType::F32)
+    hipLaunchKernelGGL(assemble0_k<float>, grid1((long)h * w, n_views), dim3(TPB), 0, s, views, L0,
+                       cam_stride, h, w, (float*)x, ld, t_plane);
+  else
+    hipLaunchKernelGGL(assemble0_k<bf16>, grid1((long)h * w, n_views), dim3(TPB), 0, s, views, L0,
+                       cam_stride, h, w, (bf16*)x, ld, t_plane);
+  return hipGetLastError();
+}
+
+hipError_t launch_transition(const ViewDesc* views, int n_views, const float* FMprev, int hp, int wp,
+                             const float* Limg, long cam_stride, int h, int w, void* x, int ld,
+                             float* FM, DType dt, int t_plane, hipStream_t s) {
+  if (n_views <= 0) return hipSuccess;
+  if (dt == DType::F32)
+    hipLaunchKernelGGL(transition_k<float>, grid1((long)h * w, n_views), dim3(TPB), 0, s, views,
+                       FMprev, hp, wp, Limg, cam_stride, h, w, (float*)x, ld, FM, t_plane);
+  else
+    hipLaunchKernelGGL(transition_k<bf16>, grid1((long)h * w, n_views), dim3(TPB), 0, s, views,
+                       FMprev, hp, wp, Limg, cam_stride, h, w, (bf16*)x, ld, FM, t_plane);
+  return hipGetLastError();
+}
+
+hipError_t launch_final(const ViewDesc* views, int n_views, const float* FM, const float* X4,
+                        long cam_stride, int h, int w, float* I2, void* x0u, int ld, DType dt,
+                        hipStream_t s) {
+  if (n_views <= 0) return hipSuccess;
+  if (dt == DType::F32)
+    hipLaunchKernelGGL(final_k<float>, grid1((long)h * w, n_views), dim3(TPB), 0, s, views, FM, X4,
+                       cam_stride, h, w, I2, (float*)x0u, ld);
+  else
+    hipLaunchKernelGGL(final_k<bf16>, grid1((long)h * w, n_views), dim3(TPB), 0, s, views, FM, X4,
+                       cam_stride, h, w, I2, (bf16*)x0u, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_flow_down(const float* in, int in_ld, int n_img, int h, int w, float* out,
+                            hipStream_t s) {
+  if (n_img <= 0) return hipSuccess;
+  hipLaunchKernelGGL(flow_down_k, grid1((long)(h / 2) * (w / 2), n_img), dim3(TPB), 0, s, in, in_ld,
+                     h, w, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ctx_warp(const ViewDesc* views, int n_views, const void* feat, long cam_stride,
+                           int C, const float* flow, int h, int w, void* dst, int dst_ld,
+                           long dst_img_stride, DType dt, hipStream_t s) {
+  if (n_views <= 0) return hipSuccess;
+  if (C % 8 != 0) return hipErrorInvalidValue;
+  const long n = (long)h * w * (C / 4);
+  if (dt == DType::F32)
+    hipLaunchKernelGGL(ctx_warp_k<float>, grid1(n, n_views), dim3(TPB), 0, s, views,
+                       (const float*)feat, cam_stride, C, flow, h, w, (float*)dst, dst_ld,
+                       dst_img_stride);
+  else
+    hipLaunchKernelGGL(ctx_warp_k<bf16>, grid1(n, n_views), dim3(TPB), 0, s, views,
+                       (const bf16*)feat, cam_stride, C, flow, h, w, (bf16*)dst, dst_ld,
+                       dst_img_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_head(const void* u4, int ld, int C, const float* w, const float* b,
+                       const float* I2, int n_img, int Hp, int Wp, int H, int W, float* out,
+                       DType dt, hipStream_t s) {
+  if (n_img <= 0) return hipSuccess;
+  if (C > 64 || C > ld) return hipErrorInvalidValue;
+  if (dt == DType::F32)
+    hipLaunchKernelGGL(head_k<float>, grid1((long)H * W, n_img), dim3(TPB), 0, s,
+                       (const float*)u4, ld, C, w, b, I2, Hp, Wp, H, W, out);
+  else
+    hipLaunchKernelGGL(head_k<bf16>, grid1((long)H * W, n_img), dim3(TPB), 0, s,
+                       (const bf16*)u4, ld, C, w, b, I2, Hp, Wp, H, W, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract(const void* src, DType dt, int ld, int C, long n_pix, float* dst,
+                          hipStream_t s) {
+  if (n_pix <= 0) return hipSuccess;
+  if (dt == DType::F32)
+    hipLaunchKernelGGL(extract_k<float>, grid1(n_pix, 1), dim3(TPB), 0, s, (const float*)src, ld, C,
+                       n_pix, dst);
+  else
+    hipLaunchKernelGGL(extract_k<bf16>, grid1(n_pix, 1), dim3(TPB), 0, s, (const bf16*)src, ld, C,
+                       n_pix, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_nhwc(const float* src, int n_img, int C, int H, int W, void* dst, int ld,
+                            DType dt, hipStream_t s) {
+  if (n_img <= 0) return hipSuccess;
+  if (dt == DType::F32)
+    hipLaunchKernelGGL(pack_nhwc_k<float>, grid1((long)H * W, n_img), dim3(TPB), 0, s, src, C, H, W,
+                       (float*)dst, ld);
+  else
+    hipLaunchKernelGGL(pack_nhwc_k<bf16>, grid1((long)H * W, n_img), dim3(TPB), 0, s, src, C, H, W,
+                       (bf16*)dst, ld);
+  return hipGetLastError();
+}
+
+}  // namespace ffv

@@ -1,0 +1,207 @@
+"""ctypes binding of libffv.so (include/ffv.h): argument marshalling only.
+
+Every step of the view-interpolation forward pass runs in the library's HIP
+kernels; this module passes torch device pointers and a HIP stream through.
+There is no fallback: if the library is missing the import of ``lib()``
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libffv.so")
+
+FFV_ABI_VERSION = 1
+FFV_FP32, FFV_BF16, FFV_FP8_E4M3 = 0, 1, 2
+PRECISIONS = {"fp32": FFV_FP32, "bf16": FFV_BF16, "fp8": FFV_FP8_E4M3}
+
+STATUS = {0: "FFV_OK", 1: "FFV_PENDING", -1: "FFV_ERR_ARG", -2: "FFV_ERR_OOM",
+          -3: "FFV_ERR_BUDGET", -4: "FFV_ERR_DEVICE", -5: "FFV_ERR_WEIGHTS",
+          -6: "FFV_ERR_TICKET", -7: "FFV_ERR_STATE"}
+
+# Every symbol include/ffv.h declares.
+EXPORTS = ["ffv_default_opts", "ffv_create_net", "ffv_destroy_net", "ffv_interpolate",
+           "ffv_last_error", "ffv_debug_tap", "ffv_set_debug", "ffv_set_profiling",
+           "ffv_kernel_stats", "ffv_op_conv"]
+
+
+class FfvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class ffv_opts(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("stream", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
+                ("hbm_budget_bytes", ctypes.c_uint64), ("tick_ms", ctypes.c_float),
+                ("max_batch_views", ctypes.c_int32)]
+
+
+class ffv_pair(ctypes.Structure):
+    _fields_ = [("left", ctypes.c_void_p), ("right", ctypes.c_void_p),
+                ("height", ctypes.c_int32), ("width", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libffv.so (built in-tree); raise if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2112_10603_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    c_int, c_void, c_f, c_sz = ctypes.c_int32, ctypes.c_void_p, ctypes.c_float, ctypes.c_size_t
+    L.ffv_default_opts.argtypes = [ctypes.POINTER(ffv_opts)]
+    L.ffv_default_opts.restype = None
+    L.ffv_create_net.argtypes = [ctypes.c_char_p, ctypes.POINTER(ffv_opts), ctypes.POINTER(c_void)]
+    L.ffv_create_net.restype = c_int
+    L.ffv_destroy_net.argtypes = [c_void]
+    L.ffv_destroy_net.restype = None
+    L.ffv_interpolate.argtypes = [c_void, ctypes.POINTER(ffv_pair), c_int, ctypes.POINTER(c_f),
+                                  c_int, c_void]
+    L.ffv_interpolate.restype = c_int
+    L.ffv_last_error.argtypes = []
+    L.ffv_last_error.restype = ctypes.c_char_p
+    L.ffv_debug_tap.argtypes = [c_void, ctypes.c_char_p, c_void, c_sz, ctypes.POINTER(c_int)]
+    L.ffv_debug_tap.restype = c_int
+    L.ffv_set_debug.argtypes = [c_void, c_int]
+    L.ffv_set_debug.restype = c_int
+    L.ffv_set_profiling.argtypes = [c_void, c_int]
+    L.ffv_set_profiling.restype = c_int
+    L.ffv_kernel_stats.argtypes = [c_void, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    L.ffv_kernel_stats.restype = c_int
+    L.ffv_op_conv.argtypes = [c_int, c_void, c_int, c_int, c_int, c_int, c_void, c_void, c_int,
+                              c_int, c_int, c_int, c_void, c_void]
+    L.ffv_op_conv.restype = c_int
+    _lib = L
+    return L
+
+
+def _check(code: int) -> int:
+    if code < 0:
+        msg = lib().ffv_last_error()
+        raise FfvError(code, msg.decode() if msg else "")
+    return code
+
+
+def _dev_f32(x: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.float32:
+        raise TypeError(f"{name} must be a float32 CUDA tensor")
+    if not x.is_contiguous():
+        raise TypeError(f"{name} must be contiguous")
+    return x
+
+
+class Net:
+    """A loaded network on one GPU. ``precision`` is "fp32" or "bf16"."""
+
+    def __init__(self, weights_path: str, precision: str = "fp32", device: int = 0,
+                 workspace_bytes: int = 0):
+        L = lib()
+        self.device = torch.device("cuda", device)
+        # The library works on this stream; calls order it after the caller's
+        # current stream.
+        self.stream = torch.cuda.Stream(device=self.device)
+        opts = ffv_opts()
+        L.ffv_default_opts(ctypes.byref(opts))
+        opts.precision = PRECISIONS[precision]
+        opts.device = device
+        opts.stream = self.stream.cuda_stream
+        opts.workspace_bytes = workspace_bytes
+        h = ctypes.c_void_p()
+        _check(L.ffv_create_net(os.fsencode(weights_path), ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+        self.precision = precision
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ffv_destroy_net(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def interpolate(self, pairs, ts, out: torch.Tensor | None = None) -> torch.Tensor:
+        """``pairs``: list of (left, right) [3, H, W] float32 CUDA tensors.
+        ``ts``: phases in [0, 1]. Returns [n_pairs, n_t, 3, H, W] float32."""
+        pairs = list(pairs)
+        ts = [float(t) for t in ts]
+        if not pairs or not ts:
+            raise ValueError("need at least one pair and one t")
+        H, W = pairs[0][0].shape[-2:]
+        arr = (ffv_pair * len(pairs))()
+        for i, (l, r) in enumerate(pairs):
+            _dev_f32(l, "left")
+            _dev_f32(r, "right")
+            if l.dim() != 3 or l.shape[0] != 3 or l.shape != r.shape:
+                raise ValueError("views must be [3, H, W] and equal in shape")
+            arr[i] = ffv_pair(l.data_ptr(), r.data_ptr(), int(l.shape[1]), int(l.shape[2]))
+        if out is None:
+            out = torch.empty((len(pairs), len(ts), 3, H, W), dtype=torch.float32,
+                              device=pairs[0][0].device)
+        _dev_f32(out, "out")
+        if out.numel() != len(pairs) * len(ts) * 3 * H * W:
+            raise ValueError("out has the wrong size")
+        tarr = (ctypes.c_float * len(ts))(*ts)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        _check(lib().ffv_interpolate(self._h, arr, len(pairs), tarr, len(ts), out.data_ptr()))
+        return out
+
+    def set_debug(self, on: bool = True):
+        _check(lib().ffv_set_debug(self._h, 1 if on else 0))
+
+    def debug_tap(self, name: str) -> torch.Tensor:
+        cap = 1 << 26
+        buf = torch.empty(cap, dtype=torch.float32, device=self.device)
+        dims = (ctypes.c_int32 * 3)()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        _check(lib().ffv_debug_tap(self._h, name.encode(), buf.data_ptr(), cap, dims))
+        c, h, w = dims[0], dims[1], dims[2]
+        return buf[: c * h * w].view(c, h, w).clone()
+
+    def set_profiling(self, on: bool = True):
+        _check(lib().ffv_set_profiling(self._h, 1 if on else 0))
+
+    def kernel_stats(self, name: str):
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        work = ctypes.c_double()
+        _check(lib().ffv_kernel_stats(self._h, name.encode(), ctypes.byref(n), ctypes.byref(ms),
+                                      ctypes.byref(work)))
+        return {"launches": n.value, "ms": ms.value, "work": work.value}
+
+
+def op_conv(x: torch.Tensor, weight, bias, stride: int = 1, transposed: bool = False,
+            relu: bool = False, precision: str = "fp32") -> torch.Tensor:
+    """One conv layer through the library's implicit-GEMM kernel.
+    ``x``: [n, cin, h, w] float32 CUDA; ``weight``/``bias``: host arrays in
+    the weights-file layout."""
+    import numpy as np
+    _dev_f32(x, "x")
+    n, cin, h, w = x.shape
+    wt = np.ascontiguousarray(weight, dtype=np.float32)
+    bs = np.ascontiguousarray(bias, dtype=np.float32)
+    cout = wt.shape[1] if transposed else wt.shape[0]
+    if transposed:
+        ho, wo = 2 * h, 2 * w
+    else:
+        ho, wo = (h - 1) // stride + 1, (w - 1) // stride + 1
+    y = torch.empty((n, cout, ho, wo), dtype=torch.float32, device=x.device)
+    s = torch.cuda.current_stream(x.device)
+    _check(lib().ffv_op_conv(PRECISIONS[precision], x.data_ptr(), n, cin, h, w,
+                             wt.ctypes.data, bs.ctypes.data, cout, stride, 1 if transposed else 0,
+                             1 if relu else 0, y.data_ptr(), s.cuda_stream))
+    return y

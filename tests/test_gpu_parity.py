@@ -1,0 +1,188 @@
+"""Whole-network parity: the HIP path (through the C ABI) against the FP64
+oracle on the same seeded inputs and weights.
+
+Bars: FP32 max-abs <= 1e-4 on [0, 1] pixels; BF16 PSNR >= 45 dB; the
+closed-form structured-weight cases exact up to fp32 rounding."""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import vinet as O
+from synth import scenes
+from synth.weights import write_weights_file
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def psnr(a, b):
+    mse = float(np.mean((np.asarray(a, np.float64) - np.asarray(b, np.float64)) ** 2))
+    return float("inf") if mse == 0 else 10 * math.log10(1.0 / mse)
+
+
+@pytest.fixture(scope="module")
+def wfile(tmp_path_factory):
+    return write_weights_file(str(tmp_path_factory.mktemp("w") / "w0.ffvw"), seed=0)
+
+
+@pytest.fixture(scope="module")
+def oracle_w(wfile):
+    return O.load_weights(wfile)
+
+
+def _net(path, precision="fp32", **kw):
+    from paper_2112_10603_amd import Net
+    return Net(path, precision, 0, **kw)
+
+
+def test_small_fp32_parity_with_taps(wfile, oracle_w):
+    """128x128, right = left shifted 4 px, t = 0.5 (the small workload)."""
+    print("case small fp32 128x128", flush=True)
+    xl, xr = scenes.small_pair()
+    net = _net(wfile)
+    net.set_debug(True)
+    out = net.interpolate([(xl.to(DEV), xr.to(DEV))], [0.5])[0, 0].cpu().numpy()
+    taps = {}
+    ref = O.vinet_forward(xl.numpy(), xr.numpy(), 0.5, oracle_w, taps)
+    for s in range(3):
+        g = net.debug_tap(f"F{s}").cpu().numpy()
+        want = np.concatenate([taps[f"F{s}"], taps[f"M{s}"]])
+        e = np.abs(g - want).max()
+        print(f"  stage {s} flow/mask max-abs {e:.3e} (|F| max {np.abs(want).max():.2f})")
+        assert e < 1e-3, (s, e)
+    i2 = net.debug_tap("I2").cpu().numpy()
+    e = np.abs(i2 - taps["I2"]).max()
+    print(f"  I2 max-abs {e:.3e}")
+    assert e < 1e-4
+    err = np.abs(out - ref).max()
+    print(f"  output max-abs {err:.3e}")
+    assert err <= 1e-4
+    net.close()
+
+
+@pytest.mark.parametrize("H,W,t", [(72, 136, 0.3), (48, 50, 1.0), (33, 17, 0.0)])
+def test_ragged_fp32_parity(wfile, oracle_w, H, W, t):
+    """Sizes that are not multiples of 16 (replicate pad + crop), several
+    tiles and a ragged tail in every conv."""
+    print(f"case ragged fp32 {H}x{W} t={t}", flush=True)
+    xl, xr = scenes.random_pair(21, H, W, d_max=5.0)
+    net = _net(wfile)
+    out = net.interpolate([(xl.to(DEV), xr.to(DEV))], [t])[0, 0].cpu().numpy()
+    ref = O.vinet_forward(xl.numpy(), xr.numpy(), t, oracle_w)
+    err = np.abs(out - ref).max()
+    print(f"  max-abs {err:.3e}")
+    assert err <= 1e-4
+    net.close()
+
+
+def test_zero_heads_closed_form(tmp_path):
+    print("case zero heads", flush=True)
+    p = write_weights_file(str(tmp_path / "z.ffvw"), seed=3, kind="zero_heads")
+    xl, xr = scenes.random_pair(7, 40, 72)
+    for prec in ("fp32", "bf16"):
+        net = _net(p, prec)
+        out = net.interpolate([(xl.to(DEV), xr.to(DEV))], [0.3])[0, 0].cpu().numpy()
+        want = 0.5 * (xl.numpy().astype(np.float64) + xr.numpy().astype(np.float64))
+        err = np.abs(out - want).max()
+        print(f"  {prec} max-abs {err:.3e}")
+        assert err <= 1e-6
+        net.close()
+
+
+def test_constant_flow_closed_form(tmp_path):
+    """Flow (2, 0, -2, 0), mask 1/2, zero residual: the exact middle view of
+    a pair 4 px apart (except the 2 clamped columns on each side)."""
+    print("case constant flow", flush=True)
+    p = write_weights_file(str(tmp_path / "c.ffvw"), seed=0, kind="const_flow")
+    xl, xr = scenes.small_pair()
+    for prec in ("fp32", "bf16"):
+        net = _net(p, prec)
+        out = net.interpolate([(xl.to(DEV), xr.to(DEV))], [0.5])[0, 0].cpu().numpy()
+        W = xl.shape[2]
+        err = np.abs(out[:, :, 2:W - 2] - xl.numpy()[:, :, 4:]).max()
+        print(f"  {prec} max-abs {err:.3e}")
+        assert err <= 1e-6
+        assert np.isfinite(out).all()
+        net.close()
+
+
+def test_batched_pairs_and_phases_match_single(wfile, oracle_w):
+    """3 pairs (sharing cameras) x 3 phases in one call: every view equals
+    the same view computed alone, bit for bit (the kernels' arithmetic per
+    output does not depend on the batch), and matches the oracle."""
+    print("case batch invariance", flush=True)
+    arc = scenes.camera_arc(31, 64, 96, 4, 96, (3.0, 10.0), 6.0, 0.01).to(DEV)
+    pairs = [(arc[i], arc[i + 1]) for i in range(3)]
+    ts = [0.25, 0.5, 0.75]
+    for prec in ("fp32", "bf16"):
+        net = _net(wfile, prec)
+        batch = net.interpolate(pairs, ts).cpu()
+        for i in range(3):
+            for j, t in enumerate(ts):
+                alone = net.interpolate([pairs[i]], [t])[0, 0].cpu()
+                assert torch.equal(alone, batch[i, j]), (prec, i, j)
+        if prec == "fp32":
+            ref = O.vinet_forward(arc[1].cpu().numpy(), arc[2].cpu().numpy(), 0.75, oracle_w)
+            assert np.abs(batch[1, 2].numpy() - ref).max() <= 1e-4
+        net.close()
+
+
+def test_chunked_workspace_matches(wfile):
+    """A workspace cap that forces one view per chunk gives identical views."""
+    print("case chunking", flush=True)
+    arc = scenes.camera_arc(32, 48, 64, 3, 64, (3.0, 8.0), 4.0, 0.01).to(DEV)
+    pairs = [(arc[0], arc[1]), (arc[1], arc[2])]
+    a = _net(wfile, "bf16")
+    full = a.interpolate(pairs, [0.1, 0.9]).cpu()
+    a.close()
+    b = _net(wfile, "bf16", workspace_bytes=1)
+    small = b.interpolate(pairs, [0.1, 0.9]).cpu()
+    b.close()
+    assert torch.equal(full, small)
+
+
+def test_bf16_psnr_small(wfile, oracle_w):
+    print("case bf16 psnr 128", flush=True)
+    xl, xr = scenes.small_pair()
+    net = _net(wfile, "bf16")
+    out = net.interpolate([(xl.to(DEV), xr.to(DEV))], [0.5])[0, 0].cpu().numpy()
+    ref = O.vinet_forward(xl.numpy(), xr.numpy(), 0.5, oracle_w)
+    p = psnr(out, ref)
+    print(f"  PSNR {p:.2f} dB, max-abs {np.abs(out - ref).max():.3e}")
+    assert p >= 45.0
+    net.close()
+
+
+def test_bf16_psnr_hd_crop(wfile, oracle_w):
+    """A 256x384 crop of the 1080p arc (blob sizes and disparities of the
+    1080p workload)."""
+    print("case bf16 psnr hd crop", flush=True)
+    arc = scenes.hd_arc(2)
+    xl = arc[0, :, 400:656, 700:1084].contiguous()
+    xr = arc[1, :, 400:656, 700:1084].contiguous()
+    net = _net(wfile, "bf16")
+    out = net.interpolate([(xl.to(DEV), xr.to(DEV))], [0.5])[0, 0].cpu().numpy()
+    ref = O.vinet_forward(xl.numpy(), xr.numpy(), 0.5, oracle_w)
+    p = psnr(out, ref)
+    print(f"  PSNR {p:.2f} dB")
+    assert p >= 45.0
+    net.close()
+
+
+def test_argument_errors(wfile):
+    from paper_2112_10603_amd import FfvError
+    net = _net(wfile)
+    x = torch.rand(3, 32, 32, device=DEV)
+    with pytest.raises(FfvError) as e:
+        net.interpolate([(x, x)], [1.5])
+    assert e.value.code == -1
+    with pytest.raises(FfvError):
+        net.interpolate([(x, x)], [float("nan")])
+    y = torch.rand(3, 32, 48, device=DEV)
+    with pytest.raises(FfvError):
+        net.interpolate([(x, x), (y, y)], [0.5])
+    net.close()
