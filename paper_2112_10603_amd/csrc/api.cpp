@@ -200,7 +200,7 @@ extern "C" ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, 
     a.cout_pad = L.cout_pad;
     a.n_img = n;
     a.stride = L.transposed ? 1 : stride;
-    a.transposed = L.transposed ? 1 : 0;
+    a.transposed = L.mode;
     a.relu = relu ? 1 : 0;
     a.out_f32 = 1;
     a.accumulate = 0;

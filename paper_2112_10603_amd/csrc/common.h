@@ -43,16 +43,19 @@ struct ConvArgs {
   int cout_pad;         // rows per phase in the packed weights
   int n_img;
   int stride;           // 1 or 2 (conv); 1 for transposed
-  int transposed;       // 0: 3x3 conv, 1: 4x4 s2 transposed (blockIdx.z = phase)
+  int transposed;       // 0: 3x3 conv; 1: 4x4 s2 transposed, one output phase per
+                        // blockIdx.z; 2: 4x4 s2 transposed, phase-merged (n = phase*cout + o)
   int relu;
   int out_f32;          // 1: float output, 0: activation dtype
   int accumulate;       // 1: add into the existing float output
 };
 
-// Tile shapes the conv kernel is instantiated for.
-enum class ConvTile : int { M128_N128 = 0, M128_N64 = 1, M128_N32 = 2 };
+// N-tile widths the conv kernel is instantiated for (the M tile is 256).
+enum class ConvTile : int { N256 = 0, N128 = 1, N64 = 2, N32 = 3 };
 
 hipError_t launch_conv(DType dt, ConvTile tile, const ConvArgs& a, hipStream_t s);
+// K elements per pipeline step of the conv kernel for a dtype.
+int conv_k_step(DType dt);
 
 // Per-view description for per-pixel kernels.
 struct ViewDesc {

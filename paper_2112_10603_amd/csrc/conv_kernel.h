@@ -1,0 +1,303 @@
+// Implicit-GEMM convolution kernel template for CDNA4 matrix cores (gfx950).
+//
+// Covers every convolution of the network (supplementary layer table):
+// 3x3 convs with padding 1 and stride 1 or 2, and 4x4 stride-2 padding-1
+// transposed convs. A transposed conv runs either per output phase (four
+// 2x2-tap convs over the input grid, blockIdx.z = phase) or, when it has few
+// output channels, phase-merged: one 3x3-neighbourhood conv over the input
+// grid whose N dimension holds (phase, channel), so the input tile is read
+// once for all four phases.
+//
+// GEMM view: M = output pixels (images folded in), N = output channels,
+// K = (tap, input channel). A workgroup of WM x WN waves computes a BM x BN
+// tile; each wave owns a block of 32x32 MFMA fragments. Each K step covers
+// KB bytes of every A and B row: the A tile is gathered from NHWC
+// activations (zero outside the image), the B tile read from packed weights
+// (K contiguous), both staged through LDS with a 16-byte-chunk XOR swizzle
+// so the MFMA operand reads do not collide on banks. STAGES = 1: register
+// prefetch of the next step, two barriers per step; STAGES = 2: double
+// buffered LDS, one barrier per step. Tiles along M are assigned so that
+// each XCD works on a contiguous range of output rows (its L2 keeps the
+// shared input rows).
+//
+// Inside a K step, lane half h = lane/32 owns one half of the step's k
+// range; the MFMA's k positions are fed in that order for both operands, so
+// the sum over k is the full dot product whatever the instruction's internal
+// k order. Accumulation is fp32 in every precision.
+#pragma once
+
+#include "common.h"
+
+namespace ffv {
+namespace convk {
+
+template <typename T>
+__device__ inline void mfma_chunk(f32x16& acc, const uint4& a, const uint4& b);
+
+// 16 bytes = 8 bf16 k-values per lane: one 32x32x16 MFMA.
+template <>
+__device__ inline void mfma_chunk<bf16>(f32x16& acc, const uint4& a, const uint4& b) {
+  bf16x8 av = __builtin_bit_cast(bf16x8, a);
+  bf16x8 bv = __builtin_bit_cast(bf16x8, b);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+}
+
+// 16 bytes = 4 fp32 k-values per lane: four 32x32x2 MFMAs.
+template <>
+__device__ inline void mfma_chunk<float>(f32x16& acc, const uint4& a, const uint4& b) {
+  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.x), __uint_as_float(b.x), acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(b.y), acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.z), __uint_as_float(b.z), acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.w), __uint_as_float(b.w), acc, 0, 0, 0);
+}
+
+template <typename T>
+__device__ inline void store_out(const ConvArgs& a, long off, float v) {
+  if (a.out_f32) {
+    float* o = reinterpret_cast<float*>(a.out) + off;
+    if (a.accumulate) v += *o;
+    *o = v;
+  } else {
+    reinterpret_cast<T*>(a.out)[off] = (T)v;
+  }
+}
+
+template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES>
+struct Conv {
+  static constexpr int NT = 64 * WM * WN;
+  static constexpr int CH = KB / 16;            // 16-byte chunks per row per step
+  static constexpr int BK = KB / (int)sizeof(T);
+  static constexpr int VEC = 16 / (int)sizeof(T);
+  static constexpr int TM = BM / WM, TN = BN / WN;
+  static constexpr int FM = TM / 32, FN = TN / 32;
+  static constexpr int A_VECS = BM * CH, B_VECS = BN * CH;
+  static constexpr int A_IT = (A_VECS + NT - 1) / NT;
+  static constexpr int B_IT = (B_VECS + NT - 1) / NT;
+  static constexpr int LDS_BYTES = STAGES * (BM + BN) * KB;
+  static_assert(FM >= 1 && FN >= 1, "wave tile >= 32x32");
+  static_assert(NT % CH == 0, "chunk of a thread is fixed");
+  static_assert(CH == 4 || CH == 8, "64- or 128-byte steps");
+
+  // physical chunk: XOR-swizzled so 8 consecutive rows cover distinct banks
+  __device__ static inline int swz(int row, int chunk) {
+    return row * CH + (chunk ^ ((row / (8 / CH)) & (CH - 1)));
+  }
+};
+
+template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES>
+__global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
+  using C = Conv<T, BM, BN, WM, WN, KB, STAGES>;
+  constexpr int NT = C::NT, CH = C::CH, BK = C::BK, VEC = C::VEC;
+  constexpr int TM = C::TM, TN = C::TN, FM = C::FM, FN = C::FN;
+  constexpr int A_IT = C::A_IT, B_IT = C::B_IT;
+
+  __shared__ __attribute__((aligned(16))) uint4 As[STAGES][BM * CH];
+  __shared__ __attribute__((aligned(16))) uint4 Bs[STAGES][BN * CH];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int merged = a.transposed == 2;
+  const int phase = a.transposed == 1 ? (int)blockIdx.z : 0;
+  const int py = phase >> 1, px = phase & 1;
+
+  // XCD-aware M-tile order: consecutive workgroup ids go round-robin over
+  // the 8 XCDs; give each XCD a contiguous range of tiles.
+  const int gx = gridDim.x;
+  const int bx = blockIdx.x;
+  const int xcd = bx & 7, q = gx >> 3, r = gx & 7;
+  const int mt = xcd * q + min(xcd, r) + (bx >> 3);
+
+  const long HW = (long)a.Ho * a.Wo;
+  const long M = (long)a.n_img * HW;
+  const long m0 = (long)mt * BM;
+  const int n0 = blockIdx.y * BN;
+  const int chunk = tid % CH;  // this thread's chunk within a row
+
+  const T* in = reinterpret_cast<const T*>(a.in);
+  const T* wgt = reinterpret_cast<const T*>(a.wgt) + (long)phase * a.cout_pad * a.K_pad;
+
+  const T* a_base[A_IT];
+  int a_iy[A_IT], a_ix[A_IT];
+  bool a_ok[A_IT];
+#pragma unroll
+  for (int i = 0; i < A_IT; ++i) {
+    const int v = tid + i * NT;
+    const int row = v / CH;
+    const long m = m0 + row;
+    a_ok[i] = (v < C::A_VECS) && (m < M);
+    const long mm = a_ok[i] ? m : 0;
+    const long img = mm / HW;
+    const int rem = (int)(mm - img * HW);
+    const int oy = rem / a.Wo;
+    const int ox = rem - oy * a.Wo;
+    a_base[i] = in + img * a.in_img_stride;
+    a_iy[i] = oy * a.stride;
+    a_ix[i] = ox * a.stride;
+  }
+
+  uint4 ra[A_IT], rb[B_IT];
+  const int nk = a.K_pad / BK;
+
+  auto gather = [&](int kc) {
+    const int k0 = kc * BK + chunk * VEC;
+    int dy = 0, dx = 0, c = 0;
+    const bool kin = k0 < a.K;
+    if (kin) {
+      const int tap = k0 / a.cin_pad;
+      c = k0 - tap * a.cin_pad;
+      if (a.transposed == 1) {
+        dy = py - (tap >> 1);
+        dx = px - (tap & 1);
+      } else {
+        dy = tap / 3 - 1;
+        dx = tap - (tap / 3) * 3 - 1;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < A_IT; ++i) {
+      const int iy = a_iy[i] + dy, ix = a_ix[i] + dx;
+      if (kin && a_ok[i] && iy >= 0 && iy < a.Hi && ix >= 0 && ix < a.Wi)
+        ra[i] = *reinterpret_cast<const uint4*>(a_base[i] + ((long)iy * a.Wi + ix) * a.in_ld + c);
+      else
+        ra[i] = make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < B_IT; ++i) {
+      const int v = tid + i * NT;
+      if (v < C::B_VECS) {
+        const int n = n0 + v / CH;
+        rb[i] = *reinterpret_cast<const uint4*>(wgt + (long)n * a.K_pad + (long)kc * BK + chunk * VEC);
+      }
+    }
+  };
+
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < A_IT; ++i) {
+      const int v = tid + i * NT;
+      if (v < C::A_VECS) As[buf][C::swz(v / CH, chunk)] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < B_IT; ++i) {
+      const int v = tid + i * NT;
+      if (v < C::B_VECS) Bs[buf][C::swz(v / CH, chunk)] = rb[i];
+    }
+  };
+
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  const int lrow = lane & 31;
+  const int lhalf = lane >> 5;
+
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < CH / 2; ++s) {
+      const int ch = lhalf * (CH / 2) + s;
+      uint4 fa[FM], fb[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) fa[i] = As[buf][C::swz(wm * TM + i * 32 + lrow, ch)];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) fb[j] = Bs[buf][C::swz(wn * TN + j * 32 + lrow, ch)];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) mfma_chunk<T>(acc[i][j], fa[i], fb[j]);
+    }
+  };
+
+  if constexpr (STAGES == 2) {
+    gather(0);
+    stash(0);
+    __syncthreads();
+    for (int kc = 0; kc < nk; ++kc) {
+      const int buf = kc & 1;
+      if (kc + 1 < nk) gather(kc + 1);
+      compute(buf);
+      if (kc + 1 < nk) stash(buf ^ 1);
+      __syncthreads();
+    }
+  } else {
+    gather(0);
+    for (int kc = 0; kc < nk; ++kc) {
+      __syncthreads();
+      stash(0);
+      __syncthreads();
+      if (kc + 1 < nk) gather(kc + 1);
+      compute(0);
+    }
+  }
+
+  // Epilogue: bias, ReLU, optional accumulate, store (NHWC, channel slice).
+  const int cout_m = merged ? a.cout : 1;
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    long off_row[16];
+    bool row_ok[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int row = wm * TM + i * 32 + (e >> 2) * 8 + lhalf * 4 + (e & 3);
+      const long m = m0 + row;
+      row_ok[e] = m < M;
+      const long mm = row_ok[e] ? m : 0;
+      const long img = mm / HW;
+      const int rem = (int)(mm - img * HW);
+      int oy = rem / a.Wo;
+      int ox = rem - oy * a.Wo;
+      if (a.transposed) {  // output of the GEMM grid point (oy, ox), phase (0, 0)
+        oy *= 2;
+        ox *= 2;
+      }
+      off_row[e] = img * a.out_img_stride + ((long)(oy + py) * a.Wout + ox + px) * a.out_ld;
+    }
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int n = n0 + wn * TN + j * 32 + lrow;
+      long col;
+      int o;
+      if (!merged) {
+        if (n >= a.cout) continue;
+        o = n;
+        col = n;
+      } else {
+        if (n >= 4 * cout_m) continue;
+        const int ph = n / cout_m;
+        o = n - ph * cout_m;
+        col = ((long)(ph >> 1) * a.Wout + (ph & 1)) * a.out_ld + o;
+      }
+      const float bn = a.bias[o];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        if (!row_ok[e]) continue;
+        float v = acc[i][j][e] + bn;
+        if (a.relu) v = fmaxf(v, 0.f);
+        store_out<T>(a, off_row[e] + col, v);
+      }
+    }
+  }
+}
+
+template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES>
+hipError_t launch_variant(const ConvArgs& a, hipStream_t s) {
+  using C = Conv<T, BM, BN, WM, WN, KB, STAGES>;
+  const long M = (long)a.n_img * a.Ho * a.Wo;
+  const int phases = a.transposed == 1 ? 4 : 1;
+  if (a.K_pad % C::BK != 0 || a.cin_pad % C::VEC != 0 || a.cout_pad % BN != 0 ||
+      a.in_ld % C::VEC != 0)
+    return hipErrorInvalidValue;
+  const long tiles = (M + BM - 1) / BM;
+  if (tiles > 0x7fffffffL) return hipErrorInvalidValue;
+  dim3 grid((unsigned)tiles, (unsigned)(a.cout_pad / BN), phases);
+  hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES>), grid, dim3(C::NT), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace convk
+}  // namespace ffv

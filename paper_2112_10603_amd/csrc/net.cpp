@@ -169,29 +169,38 @@ Status read_weights_file(const std::string& path, WeightsFile& out) {
 
 void plan_layer(Layer& L) {
   L.cin_pad = round_up(L.cin, 8);
-  L.K = (L.transposed ? 4 : 9) * L.cin_pad;
-  L.K_pad = round_up(L.K, 32);
-  int bn = L.cout >= 128 ? 128 : (L.cout > 32 ? 64 : 32);
-  L.tile = bn == 128 ? ConvTile::M128_N128 : (bn == 64 ? ConvTile::M128_N64 : ConvTile::M128_N32);
-  L.cout_pad = round_up(L.cout, bn);
+  // Transposed convs with few output channels run phase-merged: the four
+  // output phases share one 3x3-neighbourhood input tile (N = 4 * cout).
+  L.mode = L.transposed ? (L.cout <= 16 ? 2 : 1) : 0;
+  L.K = (L.mode == 1 ? 4 : 9) * L.cin_pad;
+  L.K_pad = round_up(L.K, 64);  // a multiple of every dtype's K step
+  const int n = L.mode == 2 ? 4 * L.cout : L.cout;
+  const int bn = n > 128 ? 256 : (n > 64 ? 128 : (n > 32 ? 64 : 32));
+  L.tile = bn == 256 ? ConvTile::N256
+                     : (bn == 128 ? ConvTile::N128 : (bn == 64 ? ConvTile::N64 : ConvTile::N32));
+  L.cout_pad = round_up(n, bn);
 }
 
 std::vector<uint8_t> pack_layer(const Layer& L, DType dt) {
-  const int phases = L.transposed ? 4 : 1;
+  const int phases = L.mode == 1 ? 4 : 1;
   const size_t n = (size_t)phases * L.cout_pad * L.K_pad;
   std::vector<float> p(n, 0.f);
-  for (int ph = 0; ph < phases; ++ph) {
-    const int py = ph >> 1, px = ph & 1;
+  if (L.mode == 0) {
+    // k = (dy*3 + dx) * cin_pad + c  <-  w[o][c][dy][dx]
     for (int o = 0; o < L.cout; ++o) {
-      float* row = &p[((size_t)ph * L.cout_pad + o) * L.K_pad];
-      if (!L.transposed) {
-        // k = (dy*3 + dx) * cin_pad + c  <-  w[o][c][dy][dx]
-        for (int c = 0; c < L.cin; ++c)
-          for (int tap = 0; tap < 9; ++tap)
-            row[tap * L.cin_pad + c] = L.w_host[((size_t)o * L.cin + c) * 9 + tap];
-      } else {
-        // phase (py, px), tap (ty, tx): kernel index (1 - py + 2ty, 1 - px + 2tx)
-        // k = (ty*2 + tx) * cin_pad + c  <-  w[c][o][ky][kx]
+      float* row = &p[(size_t)o * L.K_pad];
+      for (int c = 0; c < L.cin; ++c)
+        for (int tap = 0; tap < 9; ++tap)
+          row[tap * L.cin_pad + c] = L.w_host[((size_t)o * L.cin + c) * 9 + tap];
+    }
+  } else if (L.mode == 1) {
+    // phase (py, px), tap (ty, tx) reads input (a + py - ty, b + px - tx) with
+    // kernel index (1 - py + 2ty, 1 - px + 2tx);
+    // k = (ty*2 + tx) * cin_pad + c  <-  w[c][o][ky][kx]
+    for (int ph = 0; ph < 4; ++ph) {
+      const int py = ph >> 1, px = ph & 1;
+      for (int o = 0; o < L.cout; ++o) {
+        float* row = &p[((size_t)ph * L.cout_pad + o) * L.K_pad];
         for (int c = 0; c < L.cin; ++c)
           for (int ty = 0; ty < 2; ++ty)
             for (int tx = 0; tx < 2; ++tx) {
@@ -199,6 +208,25 @@ std::vector<uint8_t> pack_layer(const Layer& L, DType dt) {
               row[(ty * 2 + tx) * L.cin_pad + c] =
                   L.w_host[(((size_t)c * L.cout + o) * 4 + ky) * 4 + kx];
             }
+      }
+    }
+  } else {
+    // phase-merged: row n = ph * cout + o, k = ((dy+1)*3 + (dx+1)) * cin_pad + c
+    // over the input's 3x3 neighbourhood; phase (py, px) uses the taps with
+    // ty = py - dy and tx = px - dx in {0, 1}, kernel index (1 - py + 2ty, 1 - px + 2tx).
+    for (int ph = 0; ph < 4; ++ph) {
+      const int py = ph >> 1, px = ph & 1;
+      for (int o = 0; o < L.cout; ++o) {
+        float* row = &p[((size_t)ph * L.cout + o) * L.K_pad];
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int ty = py - dy, tx = px - dx;
+            if (ty < 0 || ty > 1 || tx < 0 || tx > 1) continue;
+            const int ky = 1 - py + 2 * ty, kx = 1 - px + 2 * tx;
+            const int tap = (dy + 1) * 3 + (dx + 1);
+            for (int c = 0; c < L.cin; ++c)
+              row[tap * L.cin_pad + c] = L.w_host[(((size_t)c * L.cout + o) * 4 + ky) * 4 + kx];
+          }
       }
     }
   }
@@ -435,7 +463,7 @@ Status Net::conv(const Layer& L, const void* in, int in_ld, long in_img_stride, 
   a.cout_pad = L.cout_pad;
   a.n_img = n_img;
   a.stride = L.transposed ? 1 : L.stride;
-  a.transposed = L.transposed ? 1 : 0;
+  a.transposed = L.mode;
   a.relu = relu ? 1 : 0;
   a.out_f32 = out_f32 ? 1 : 0;
   a.accumulate = accumulate ? 1 : 0;

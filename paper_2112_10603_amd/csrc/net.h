@@ -29,7 +29,8 @@ struct Layer {
   bool transposed = false;
   int cin = 0, cout = 0, stride = 1;
   int cin_pad = 0, K = 0, K_pad = 0, cout_pad = 0;
-  ConvTile tile = ConvTile::M128_N128;
+  int mode = 0;  // ConvArgs::transposed: 0 conv, 1 per-phase transposed, 2 phase-merged
+  ConvTile tile = ConvTile::N256;
   std::vector<float> w_host;  // file layout
   std::vector<float> b_host;
   void* w_dev = nullptr;      // packed [phase][cout_pad][K_pad], activation dtype
