@@ -104,6 +104,58 @@ ffv_status ffv_interpolate(ffv_net* net, const ffv_pair* views, int32_t n_pairs,
 const char* ffv_last_error(void);
 
 /* ---------------------------------------------------------------------- */
+/* Serving (enabled when ffv_opts.hbm_budget_bytes > 0)                     */
+/* ---------------------------------------------------------------------- */
+/*
+ * Many users each ask for their own viewpoint between neighbouring cameras
+ * (the paper's multi-user setting, section 2; one network evaluation per
+ * view, section 3.1). Cameras are registered once; the library keeps each
+ * camera's padded image, its image pyramid and its context features
+ * resident in device memory, and every request reuses them. Requests are
+ * admitted in FIFO order once per tick (opts.tick_ms) or when a running
+ * batch finishes, grouped per resolution into batches of at most
+ * opts.max_batch_views, while the bytes of resident cameras plus the
+ * workspaces of batches in flight stay within opts.hbm_budget_bytes. Each
+ * batch runs on its own stream, so batches overlap on the device. A view's
+ * result does not depend on the batch it runs in.
+ */
+
+/* Copy a DEVICE planar [3][H][W] float32 image in [0,1] as camera cam_id
+ * and build its resident data (synchronous). Re-registering an id replaces
+ * the camera after the batches in flight finish. Errors: FFV_ERR_ARG,
+ * FFV_ERR_BUDGET (cameras alone exceed the budget), FFV_ERR_STATE (serving
+ * off), FFV_ERR_OOM, FFV_ERR_DEVICE. */
+ffv_status ffv_register_camera(ffv_net* net, int32_t cam_id, const float* image, int32_t height,
+                               int32_t width);
+
+typedef struct {
+  int32_t cam_left, cam_right; /* registered ids, equal sizes */
+  float t;                     /* phase in [0,1]: 0 = cam_left, 1 = cam_right */
+  float* out;                  /* DEVICE planar [3][H][W] float32, caller-owned,
+                                  valid until ffv_poll returns FFV_OK */
+  uint64_t user_tag;
+} ffv_request;
+
+typedef struct {
+  double t_submit, t_admit, t_launch, t_done; /* seconds, steady clock */
+} ffv_timing;
+
+/* Queue a request (non-blocking, thread-safe). Errors: FFV_ERR_ARG (unknown
+ * camera, sizes differ, t outside [0,1], null out), FFV_ERR_BUDGET (one view
+ * can never fit the budget), FFV_ERR_STATE (serving off). */
+ffv_status ffv_submit(ffv_net* net, const ffv_request* req, uint64_t* ticket);
+
+/* FFV_PENDING while queued or running; FFV_OK once the output is written
+ * (fills *timing if non-NULL; the ticket is then collected);
+ * FFV_ERR_TICKET for unknown or collected tickets. Thread-safe. */
+ffv_status ffv_poll(ffv_net* net, uint64_t ticket, ffv_timing* timing);
+
+/* Requests admitted and completed so far, requests queued now, and device
+ * bytes held by resident cameras plus batch workspaces. */
+ffv_status ffv_serving_stats(ffv_net* net, int64_t* admitted, int64_t* completed, int64_t* queued,
+                             uint64_t* bytes_in_use);
+
+/* ---------------------------------------------------------------------- */
 /* Instrumentation (used by tests and the benchmark)                       */
 /* ---------------------------------------------------------------------- */
 

@@ -57,6 +57,8 @@ ffv_status ffv_create_net(const char* weights_path, const ffv_opts* opts, ffv_ne
     ffv_net* n = new ffv_net();
     ffv::Status s = n->net.init(weights_path, opts->precision, opts->device,
                                 (hipStream_t)opts->stream, opts->workspace_bytes);
+    if (s.good() && opts->hbm_budget_bytes > 0)
+      s = n->net.start_serving(opts->hbm_budget_bytes, opts->tick_ms, opts->max_batch_views);
     if (!s.good()) {
       delete n;
       return from(s);
@@ -102,6 +104,65 @@ ffv_status ffv_interpolate(ffv_net* net, const ffv_pair* views, int32_t n_pairs,
 }
 
 const char* ffv_last_error(void) { return g_last_error.c_str(); }
+
+ffv_status ffv_register_camera(ffv_net* net, int32_t cam_id, const float* image, int32_t height,
+                               int32_t width) {
+  if (!net || !image) return fail(FFV_ERR_ARG, "null argument");
+  if (!net->net.server()) return fail(FFV_ERR_STATE, "serving is off (hbm_budget_bytes = 0)");
+  try {
+    return from(net->net.server()->register_camera(cam_id, image, height, width));
+  } catch (const std::exception& e) {
+    return fail(FFV_ERR_DEVICE, e.what());
+  }
+}
+
+ffv_status ffv_submit(ffv_net* net, const ffv_request* req, uint64_t* ticket) {
+  if (!net || !req || !ticket) return fail(FFV_ERR_ARG, "null argument");
+  if (!net->net.server()) return fail(FFV_ERR_STATE, "serving is off (hbm_budget_bytes = 0)");
+  ffv::Request r;
+  r.cam_l = req->cam_left;
+  r.cam_r = req->cam_right;
+  r.t = req->t;
+  r.out = req->out;
+  r.tag = req->user_tag;
+  try {
+    return from(net->net.server()->submit(r, ticket));
+  } catch (const std::exception& e) {
+    return fail(FFV_ERR_DEVICE, e.what());
+  }
+}
+
+ffv_status ffv_poll(ffv_net* net, uint64_t ticket, ffv_timing* timing) {
+  if (!net) return fail(FFV_ERR_ARG, "null argument");
+  if (!net->net.server()) return fail(FFV_ERR_STATE, "serving is off (hbm_budget_bytes = 0)");
+  ffv::Timing tm;
+  bool done = false;
+  ffv_status st = from(net->net.server()->poll(ticket, &tm, &done));
+  if (st != FFV_OK) return st;
+  if (!done) return FFV_PENDING;
+  if (timing) {
+    timing->t_submit = tm.t_submit;
+    timing->t_admit = tm.t_admit;
+    timing->t_launch = tm.t_launch;
+    timing->t_done = tm.t_done;
+  }
+  return FFV_OK;
+}
+
+ffv_status ffv_serving_stats(ffv_net* net, int64_t* admitted, int64_t* completed, int64_t* queued,
+                             uint64_t* bytes_in_use) {
+  if (!net || !admitted || !completed || !queued || !bytes_in_use)
+    return fail(FFV_ERR_ARG, "null argument");
+  if (!net->net.server()) return fail(FFV_ERR_STATE, "serving is off (hbm_budget_bytes = 0)");
+  long a = 0, c = 0, q = 0;
+  size_t b = 0;
+  ffv_status st = from(net->net.server()->stats(&a, &c, &q, &b));
+  *admitted = a;
+  *completed = c;
+  *queued = q;
+  *bytes_in_use = b;
+  return st;
+}
 
 ffv_status ffv_debug_tap(ffv_net* net, const char* name, float* dst, size_t capacity_floats,
                          int32_t dims[3]) {
@@ -163,8 +224,9 @@ extern "C" ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, 
   const int wo = L.transposed ? 2 * w : (w - 1) / stride + 1;
   std::vector<uint8_t> packed = pack_layer(L, dt);
   const size_t e = dtype_size(dt);
-  void *xin = nullptr, *wd = nullptr, *bd = nullptr, *yo = nullptr;
+  void *xin = nullptr, *wd = nullptr, *bd = nullptr, *yo = nullptr, *zr = nullptr;
   auto cleanup = [&]() {
+    if (zr) hipFree(zr);
     if (xin) hipFree(xin);
     if (wd) hipFree(wd);
     if (bd) hipFree(bd);
@@ -174,6 +236,8 @@ extern "C" ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, 
   if (err == hipSuccess) err = hipMalloc(&wd, packed.size());
   if (err == hipSuccess) err = hipMalloc(&bd, (size_t)cout * 4);
   if (err == hipSuccess) err = hipMalloc(&yo, (size_t)n * ho * wo * cout * 4);
+  if (err == hipSuccess) err = hipMalloc(&zr, 256);
+  if (err == hipSuccess) err = hipMemset(zr, 0, 256);
   if (err == hipSuccess) err = hipMemcpy(wd, packed.data(), packed.size(), hipMemcpyHostToDevice);
   if (err == hipSuccess) err = hipMemcpy(bd, bias, (size_t)cout * 4, hipMemcpyHostToDevice);
   if (err == hipSuccess) err = launch_pack_nhwc(x, n, cin, h, w, xin, L.cin_pad, dt, s);
@@ -204,6 +268,8 @@ extern "C" ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, 
     a.relu = relu ? 1 : 0;
     a.out_f32 = 1;
     a.accumulate = 0;
+    a.taps = L.mode == 1 ? 4 : 9;
+    a.zero = zr;
     err = launch_conv(dt, L.tile, a, s);
   }
   for (int i = 0; err == hipSuccess && i < n; ++i)

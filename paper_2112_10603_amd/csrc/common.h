@@ -48,6 +48,8 @@ struct ConvArgs {
   int relu;
   int out_f32;          // 1: float output, 0: activation dtype
   int accumulate;       // 1: add into the existing float output
+  int taps;             // taps in K (9, or 4 for one transposed phase)
+  const void* zero;     // >= 16 bytes of zeros (read for taps outside the image)
 };
 
 // N-tile widths the conv kernel is instantiated for (the M tile is 256).
@@ -57,40 +59,45 @@ hipError_t launch_conv(DType dt, ConvTile tile, const ConvArgs& a, hipStream_t s
 // K elements per pipeline step of the conv kernel for a dtype.
 int conv_k_step(DType dt);
 
-// Per-view description for per-pixel kernels.
-struct ViewDesc {
-  int cam_l, cam_r;  // camera slots
-  float t;           // phase
-  int pad;
+// Per-camera data on the device (all NHWC), shared by every view of the
+// camera: padded image (4 floats per pixel), its quarter- and half-size
+// copies, and the four context-feature levels (activation dtype).
+struct CamDev {
+  const float* X4;
+  const float* L0;
+  const float* L1;
+  const void* ctx[4];
 };
 
-// Per-camera resident data (all NHWC).
-struct CamPtrs {
-  const float* X4;  // padded image, 4 floats per pixel (RGB, 0), Hp x Wp
-  const float* L0;  // quarter size, 4 floats per pixel
-  const float* L1;  // half size
+// Per-view description: the two cameras (indices into the CamDev table),
+// the phase and where the view's planar [3][H][W] output goes.
+struct ViewDesc {
+  int cam_l, cam_r;
+  float t;
+  int pad;
+  float* out;
+  void* pad2;
 };
 
 hipError_t launch_ingest(const float* const* src, int n_cam, int H, int W, int Hp, int Wp,
                          float* X4, void* Xa, DType dt, hipStream_t s);
 hipError_t launch_resample4(const float* in, int n_img, int Hi, int Wi, float* out, int Ho, int Wo,
                             hipStream_t s);
-hipError_t launch_assemble0(const ViewDesc* views, int n_views, const float* L0, long cam_stride,
-                            int h, int w, void* x, int ld, DType dt, int t_plane, hipStream_t s);
-hipError_t launch_transition(const ViewDesc* views, int n_views, const float* FMprev, int hp, int wp,
-                             const float* Limg, long cam_stride, int h, int w, void* x, int ld,
+hipError_t launch_assemble0(const ViewDesc* views, int n_views, const CamDev* cams, int h, int w,
+                            void* x, int ld, DType dt, int t_plane, hipStream_t s);
+hipError_t launch_transition(const ViewDesc* views, int n_views, const CamDev* cams, int level,
+                             const float* FMprev, int hp, int wp, int h, int w, void* x, int ld,
                              float* FM, DType dt, int t_plane, hipStream_t s);
-hipError_t launch_final(const ViewDesc* views, int n_views, const float* FM, const float* X4,
-                        long cam_stride, int h, int w, float* I2, void* x0u, int ld, DType dt,
-                        hipStream_t s);
+hipError_t launch_final(const ViewDesc* views, int n_views, const CamDev* cams, const float* FM,
+                        int h, int w, float* I2, void* x0u, int ld, DType dt, hipStream_t s);
 hipError_t launch_flow_down(const float* in, int in_ld, int n_img, int h, int w, float* out,
                             hipStream_t s);
-hipError_t launch_ctx_warp(const ViewDesc* views, int n_views, const void* feat, long cam_stride,
-                           int C, const float* flow, int h, int w, void* dst, int dst_ld,
+hipError_t launch_ctx_warp(const ViewDesc* views, int n_views, const CamDev* cams, int level, int C,
+                           const float* flow, int h, int w, void* dst, int dst_ld,
                            long dst_img_stride, DType dt, hipStream_t s);
 hipError_t launch_head(const void* u4, int ld, int C, const float* w, const float* b,
-                       const float* I2, int n_img, int Hp, int Wp, int H, int W, float* out,
-                       DType dt, hipStream_t s);
+                       const float* I2, const ViewDesc* views, int n_img, int Hp, int Wp, int H,
+                       int W, DType dt, hipStream_t s);
 hipError_t launch_extract(const void* src, DType dt, int ld, int C, long n_pix, float* dst,
                           hipStream_t s);
 hipError_t launch_pack_nhwc(const float* src, int n_img, int C, int H, int W, void* dst, int ld,

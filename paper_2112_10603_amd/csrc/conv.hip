@@ -11,13 +11,13 @@ hipError_t launch_t(ConvTile tile, const ConvArgs& a, hipStream_t s) {
   using namespace convk;
   switch (tile) {
     case ConvTile::N256:
-      return launch_variant<T, 256, 256, 4, 2, 128, 2>(a, s);
+      return launch_variant<T, 256, 256, 4, 2, 128, 2, 1>(a, s);
     case ConvTile::N128:
-      return launch_variant<T, 256, 128, 4, 2, 64, 1>(a, s);
+      return launch_variant<T, 256, 128, 4, 2, 128, 2, 1>(a, s);
     case ConvTile::N64:
-      return launch_variant<T, 256, 64, 8, 1, 128, 2>(a, s);
+      return launch_variant<T, 256, 64, 8, 1, 128, 2, 1>(a, s);
     case ConvTile::N32:
-      return launch_variant<T, 256, 32, 8, 1, 128, 2>(a, s);
+      return launch_variant<T, 256, 32, 8, 1, 128, 2, 1>(a, s);
   }
   return hipErrorInvalidValue;
 }

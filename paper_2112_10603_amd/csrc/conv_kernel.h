@@ -12,13 +12,15 @@
 // K = (tap, input channel). A workgroup of WM x WN waves computes a BM x BN
 // tile; each wave owns a block of 32x32 MFMA fragments. Each K step covers
 // KB bytes of every A and B row: the A tile is gathered from NHWC
-// activations (zero outside the image), the B tile read from packed weights
-// (K contiguous), both staged through LDS with a 16-byte-chunk XOR swizzle
-// so the MFMA operand reads do not collide on banks. STAGES = 1: register
-// prefetch of the next step, two barriers per step; STAGES = 2: double
-// buffered LDS, one barrier per step. Tiles along M are assigned so that
-// each XCD works on a contiguous range of output rows (its L2 keeps the
-// shared input rows).
+// activations, the B tile read from packed weights (K contiguous). Both go
+// straight from global memory into LDS with global_load_lds_dwordx4 (no
+// register staging): a lane's load lands in the 16-byte LDS slot given by
+// its position in the workgroup, so each lane fetches the chunk that the
+// XOR swizzle (chunk ^ f(row)) places in that slot, and taps outside the
+// image read from a zero buffer. STAGES LDS buffers form a ring: the loads
+// of the next STAGES - 1 steps are in flight while step k computes; one
+// barrier per step. Tiles along M are assigned so that each XCD works on a contiguous
+// range of output rows (its L2 keeps the shared input rows).
 //
 // Inside a K step, lane half h = lane/32 owns one half of the step's k
 // range; the MFMA's k positions are fed in that order for both operands, so
@@ -51,6 +53,36 @@ __device__ inline void mfma_chunk<float>(f32x16& acc, const uint4& a, const uint
   acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.w), __uint_as_float(b.w), acc, 0, 0, 0);
 }
 
+typedef __attribute__((address_space(3))) void* lptr_t;
+
+// 16 bytes from global memory straight into LDS: lane l of the wave writes
+// dst_wave_base + 16*l (global_load_lds_dwordx4, M0 = LDS base). Issued as
+// inline asm so the compiler does not serialise it against the operand
+// reads of the other ring stage; the caller waits on vmcnt before the
+// barrier that publishes the stage. M0 is saved and restored around the
+// load, so its value is unchanged for the surrounding compiled code.
+__device__ inline void load_to_lds(const void* src, void* dst_wave_base) {
+  const uint32_t lds = __builtin_amdgcn_readfirstlane((uint32_t)(size_t)(lptr_t)dst_wave_base);
+  uint32_t saved;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\t"
+      "s_mov_b32 m0, %1\n\t"
+      "global_load_lds_dwordx4 %2, off\n\t"
+      "s_mov_b32 m0, %0"
+      : "=&s"(saved)
+      : "s"(lds), "v"(src)
+      : "memory");
+}
+
+// Wait until at most N vector-memory operations of this wave are
+// outstanding (gfx9 s_waitcnt encoding: vmcnt in bits 3:0 and 15:14; expcnt
+// and lgkmcnt left at their maxima).
+template <int N>
+__device__ inline void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
 template <typename T>
 __device__ inline void store_out(const ConvArgs& a, long off, float v) {
   if (a.out_f32) {
@@ -62,7 +94,7 @@ __device__ inline void store_out(const ConvArgs& a, long off, float v) {
   }
 }
 
-template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES>
+template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES, int SWZ = 0>
 struct Conv {
   static constexpr int NT = 64 * WM * WN;
   static constexpr int CH = KB / 16;            // 16-byte chunks per row per step
@@ -77,19 +109,29 @@ struct Conv {
   static_assert(FM >= 1 && FN >= 1, "wave tile >= 32x32");
   static_assert(NT % CH == 0, "chunk of a thread is fixed");
   static_assert(CH == 4 || CH == 8, "64- or 128-byte steps");
+  static_assert(STAGES >= 2 && STAGES <= 4, "ring of 2 to 4 stages");
+  static_assert(STAGES == 2 || (A_VECS % NT == 0 && B_VECS % NT == 0),
+                "a deeper ring needs the same load count in every wave");
 
-  // physical chunk: XOR-swizzled so 8 consecutive rows cover distinct banks
-  __device__ static inline int swz(int row, int chunk) {
-    return row * CH + (chunk ^ ((row / (8 / CH)) & (CH - 1)));
+  // XOR key of a row: SWZ 0 makes 8 consecutive rows cover distinct 16-byte
+  // bank groups of a 128-byte bank window; SWZ 1 makes 16 consecutive rows
+  // distinct in a 256-byte window.
+  __device__ static inline int key(int row) {
+    return SWZ == 0 ? ((row / (8 / CH)) & (CH - 1)) : ((row / (16 / CH)) & (CH - 1));
   }
+  // physical chunk of (row, logical chunk)
+  __device__ static inline int swz(int row, int chunk) { return row * CH + (chunk ^ key(row)); }
+  // the logical chunk stored at (row, physical chunk) (the XOR is an involution)
+  __device__ static inline int logical_chunk(int row, int phys) { return phys ^ key(row); }
 };
 
-template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES>
+template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES, int SWZ>
 __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
-  using C = Conv<T, BM, BN, WM, WN, KB, STAGES>;
+  using C = Conv<T, BM, BN, WM, WN, KB, STAGES, SWZ>;
   constexpr int NT = C::NT, CH = C::CH, BK = C::BK, VEC = C::VEC;
   constexpr int TM = C::TM, TN = C::TN, FM = C::FM, FN = C::FN;
   constexpr int A_IT = C::A_IT, B_IT = C::B_IT;
+  constexpr int A_VECS = C::A_VECS, B_VECS = C::B_VECS;
 
   __shared__ __attribute__((aligned(16))) uint4 As[STAGES][BM * CH];
   __shared__ __attribute__((aligned(16))) uint4 Bs[STAGES][BN * CH];
@@ -117,16 +159,19 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
 
   const T* in = reinterpret_cast<const T*>(a.in);
   const T* wgt = reinterpret_cast<const T*>(a.wgt) + (long)phase * a.cout_pad * a.K_pad;
+  (void)VEC;
 
+  // Per A-load row data, fixed across the K loop. Load i of this thread
+  // fills LDS slot tid + i*NT = (row, physical chunk tid % CH).
   const T* a_base[A_IT];
-  int a_iy[A_IT], a_ix[A_IT];
+  int a_iy[A_IT], a_ix[A_IT], a_ch[A_IT];
   bool a_ok[A_IT];
 #pragma unroll
   for (int i = 0; i < A_IT; ++i) {
     const int v = tid + i * NT;
     const int row = v / CH;
     const long m = m0 + row;
-    a_ok[i] = (v < C::A_VECS) && (m < M);
+    a_ok[i] = (v < A_VECS) && (m < M);
     const long mm = a_ok[i] ? m : 0;
     const long img = mm / HW;
     const int rem = (int)(mm - img * HW);
@@ -135,18 +180,44 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
     a_base[i] = in + img * a.in_img_stride;
     a_iy[i] = oy * a.stride;
     a_ix[i] = ox * a.stride;
+    a_ch[i] = C::logical_chunk(row, chunk);
   }
-
-  uint4 ra[A_IT], rb[B_IT];
+  const T* b_row[B_IT];
+  int b_ch[B_IT];
+#pragma unroll
+  for (int i = 0; i < B_IT; ++i) {
+    const int v = tid + i * NT;
+    const int row = (B_VECS % NT == 0 || v < B_VECS) ? v / CH : 0;
+    b_row[i] = wgt + (long)(n0 + row) * a.K_pad;
+    b_ch[i] = C::logical_chunk(row, chunk);
+  }
+  const T* zero = reinterpret_cast<const T*>(a.zero);
   const int nk = a.K_pad / BK;
+  const int lrow = lane & 31;
+  const int lhalf = lane >> 5;
+  // a step stays inside one tap when the channel count is a multiple of BK
+  const bool tap_uniform = (a.cin_pad % BK) == 0;
 
-  auto gather = [&](int kc) {
-    const int k0 = kc * BK + chunk * VEC;
-    int dy = 0, dx = 0, c = 0;
-    const bool kin = k0 < a.K;
-    if (kin) {
-      const int tap = k0 / a.cin_pad;
-      c = k0 - tap * a.cin_pad;
+  auto issue = [&](int kc, int buf) {
+    int tap_u = 0, c_u = 0;
+    if (tap_uniform) {
+      const int k0 = kc * BK;
+      tap_u = k0 / a.cin_pad;
+      c_u = k0 - tap_u * a.cin_pad;
+    }
+#pragma unroll
+    for (int i = 0; i < A_IT; ++i) {
+      const int kk = a_ch[i] * VEC;
+      int tap, c;
+      if (tap_uniform) {
+        tap = tap_u;
+        c = c_u + kk;
+      } else {
+        const int k0 = kc * BK + kk;
+        tap = k0 < a.K ? k0 / a.cin_pad : 9;
+        c = k0 - (k0 < a.K ? tap : 0) * a.cin_pad;
+      }
+      int dy, dx;
       if (a.transposed == 1) {
         dy = py - (tap >> 1);
         dx = px - (tap & 1);
@@ -154,35 +225,17 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
         dy = tap / 3 - 1;
         dx = tap - (tap / 3) * 3 - 1;
       }
-    }
-#pragma unroll
-    for (int i = 0; i < A_IT; ++i) {
       const int iy = a_iy[i] + dy, ix = a_ix[i] + dx;
-      if (kin && a_ok[i] && iy >= 0 && iy < a.Hi && ix >= 0 && ix < a.Wi)
-        ra[i] = *reinterpret_cast<const uint4*>(a_base[i] + ((long)iy * a.Wi + ix) * a.in_ld + c);
-      else
-        ra[i] = make_uint4(0, 0, 0, 0);
+      const bool ok = a_ok[i] && tap < a.taps && iy >= 0 && iy < a.Hi && ix >= 0 && ix < a.Wi;
+      const T* src = ok ? a_base[i] + ((long)iy * a.Wi + ix) * a.in_ld + c : zero;
+      if (A_VECS % NT == 0 || tid + i * NT < A_VECS)
+        load_to_lds(src, &As[buf][i * NT + wave * 64]);
     }
 #pragma unroll
     for (int i = 0; i < B_IT; ++i) {
-      const int v = tid + i * NT;
-      if (v < C::B_VECS) {
-        const int n = n0 + v / CH;
-        rb[i] = *reinterpret_cast<const uint4*>(wgt + (long)n * a.K_pad + (long)kc * BK + chunk * VEC);
-      }
-    }
-  };
-
-  auto stash = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < A_IT; ++i) {
-      const int v = tid + i * NT;
-      if (v < C::A_VECS) As[buf][C::swz(v / CH, chunk)] = ra[i];
-    }
-#pragma unroll
-    for (int i = 0; i < B_IT; ++i) {
-      const int v = tid + i * NT;
-      if (v < C::B_VECS) Bs[buf][C::swz(v / CH, chunk)] = rb[i];
+      const T* src = b_row[i] + (long)kc * BK + b_ch[i] * VEC;
+      if (B_VECS % NT == 0 || tid + i * NT < B_VECS)
+        load_to_lds(src, &Bs[buf][i * NT + wave * 64]);
     }
   };
 
@@ -193,9 +246,6 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
     for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
-
-  const int lrow = lane & 31;
-  const int lhalf = lane >> 5;
 
   auto compute = [&](int buf) {
 #pragma unroll
@@ -213,26 +263,23 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
     }
   };
 
-  if constexpr (STAGES == 2) {
-    gather(0);
-    stash(0);
+  // Ring of STAGES buffers: the loads of steps k+1 .. k+STAGES-1 are in
+  // flight while step k computes. The LDS loads are issued outside the
+  // compiler's view, so the waits for them are explicit: before the barrier
+  // of step k, at most the loads of the younger steps may be outstanding
+  // (vmcnt drains in issue order).
+  constexpr int LPS = A_IT + B_IT;  // loads per step per thread
+#pragma unroll
+  for (int st = 0; st < STAGES - 1; ++st)
+    if (st < nk) issue(st, st);
+  for (int kc = 0; kc < nk; ++kc) {
+    if (kc + STAGES - 2 < nk)
+      wait_vm<(STAGES - 2) * LPS>();
+    else
+      wait_vm<0>();
     __syncthreads();
-    for (int kc = 0; kc < nk; ++kc) {
-      const int buf = kc & 1;
-      if (kc + 1 < nk) gather(kc + 1);
-      compute(buf);
-      if (kc + 1 < nk) stash(buf ^ 1);
-      __syncthreads();
-    }
-  } else {
-    gather(0);
-    for (int kc = 0; kc < nk; ++kc) {
-      __syncthreads();
-      stash(0);
-      __syncthreads();
-      if (kc + 1 < nk) gather(kc + 1);
-      compute(0);
-    }
+    if (kc + STAGES - 1 < nk) issue(kc + STAGES - 1, (kc + STAGES - 1) % STAGES);
+    compute(kc % STAGES);
   }
 
   // Epilogue: bias, ReLU, optional accumulate, store (NHWC, channel slice).
@@ -284,9 +331,9 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   }
 }
 
-template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES>
+template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES, int SWZ = 0>
 hipError_t launch_variant(const ConvArgs& a, hipStream_t s) {
-  using C = Conv<T, BM, BN, WM, WN, KB, STAGES>;
+  using C = Conv<T, BM, BN, WM, WN, KB, STAGES, SWZ>;
   const long M = (long)a.n_img * a.Ho * a.Wo;
   const int phases = a.transposed == 1 ? 4 : 1;
   if (a.K_pad % C::BK != 0 || a.cin_pad % C::VEC != 0 || a.cout_pad % BN != 0 ||
@@ -295,7 +342,7 @@ hipError_t launch_variant(const ConvArgs& a, hipStream_t s) {
   const long tiles = (M + BM - 1) / BM;
   if (tiles > 0x7fffffffL) return hipErrorInvalidValue;
   dim3 grid((unsigned)tiles, (unsigned)(a.cout_pad / BN), phases);
-  hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES>), grid, dim3(C::NT), 0, s, a);
+  hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES, SWZ>), grid, dim3(C::NT), 0, s, a);
   return hipGetLastError();
 }
 

@@ -9,6 +9,7 @@
 #include "net.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <fstream>
@@ -244,7 +245,22 @@ std::vector<uint8_t> pack_layer(const Layer& L, DType dt) {
 
 // ----------------------------------------------------------------- Net
 
+Geo Geo::of(int H, int W) {
+  Geo g;
+  g.H = H;
+  g.W = W;
+  g.Hp = round_up(H, 16);
+  g.Wp = round_up(W, 16);
+  g.P = (long)g.Hp * g.Wp;
+  return g;
+}
+
+double now_seconds() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 Net::~Net() {
+  server_.reset();
   if (device_ >= 0) hipSetDevice(device_);
   if (stream_) hipStreamSynchronize(stream_);
   for (auto& kv : layers_) {
@@ -252,7 +268,7 @@ Net::~Net() {
     if (kv.second.b_dev) hipFree(kv.second.b_dev);
   }
   if (ws_) hipFree(ws_);
-  if (src_ptrs_) hipFree(src_ptrs_);
+  if (zero_) hipFree(zero_);
   for (auto& e : pending_) {
     hipEventDestroy(e.a);
     hipEventDestroy(e.b);
@@ -261,11 +277,17 @@ Net::~Net() {
   if (own_stream_ && stream_) hipStreamDestroy(stream_);
 }
 
-Status Net::check(hipError_t e, const char* what) {
+Status Net::check(hipError_t e, const char* what) const {
   if (e == hipSuccess) return Status::ok();
   const int code = (e == hipErrorOutOfMemory) ? -2 : -4;
   return Status::err(code, std::string(what) + ": " + hipGetErrorString(e));
 }
+
+#define FFV_TRY(expr)              \
+  do {                             \
+    Status _s = (expr);            \
+    if (!_s.good()) return _s;     \
+  } while (0)
 
 Status Net::init(const std::string& path, int precision, int device, hipStream_t stream,
                  size_t workspace_cap) {
@@ -275,78 +297,91 @@ Status Net::init(const std::string& path, int precision, int device, hipStream_t
   device_ = device;
   ws_cap_ = workspace_cap ? workspace_cap : (size_t)16 << 30;
   WeightsFile wf;
-  Status st = read_weights_file(path, wf);
-  if (!st.good()) return st;
+  FFV_TRY(read_weights_file(path, wf));
   base_width_ = wf.base_width;
   t_plane_ = wf.t_plane;
   if (base_width_ % 16 != 0 || base_width_ > 128)
     return Status::err(-5, "base width must be a multiple of 16, at most 128, for the GPU layouts");
   int ndev = 0;
-  st = check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
-  if (!st.good()) return st;
+  FFV_TRY(check(hipGetDeviceCount(&ndev), "hipGetDeviceCount"));
   if (device < 0 || device >= ndev) return Status::err(-1, "device ordinal out of range");
-  st = check(hipSetDevice(device), "hipSetDevice");
-  if (!st.good()) return st;
+  FFV_TRY(check(hipSetDevice(device), "hipSetDevice"));
   if (stream) {
     stream_ = stream;
   } else {
-    st = check(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking), "hipStreamCreate");
-    if (!st.good()) return st;
+    FFV_TRY(check(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking), "hipStreamCreate"));
     own_stream_ = true;
   }
+  FFV_TRY(check(hipMalloc(&zero_, 256), "hipMalloc zero"));
+  FFV_TRY(check(hipMemset(zero_, 0, 256), "hipMemset zero"));
   layers_ = std::move(wf.layers);
   for (auto& kv : layers_) {
     Layer& L = kv.second;
     plan_layer(L);
-    if (L.name == "unet.head") continue;  // evaluated by the head kernel in fp32
-    std::vector<uint8_t> packed = pack_layer(L, dt_);
-    st = check(hipMalloc(&L.w_dev, packed.size()), "hipMalloc weights");
-    if (!st.good()) return st;
-    st = check(hipMemcpy(L.w_dev, packed.data(), packed.size(), hipMemcpyHostToDevice), "copy weights");
-    if (!st.good()) return st;
-  }
-  for (auto& kv : layers_) {
-    Layer& L = kv.second;
-    const std::vector<float>& src = L.b_host;
-    st = check(hipMalloc((void**)&L.b_dev, src.size() * 4), "hipMalloc bias");
-    if (!st.good()) return st;
-    st = check(hipMemcpy(L.b_dev, src.data(), src.size() * 4, hipMemcpyHostToDevice), "copy bias");
-    if (!st.good()) return st;
-  }
-  {
-    // head weights stay fp32 in file layout [3][16][3][3]
-    Layer& H = layers_.at("unet.head");
-    st = check(hipMalloc(&H.w_dev, H.w_host.size() * 4), "hipMalloc head");
-    if (!st.good()) return st;
-    st = check(hipMemcpy(H.w_dev, H.w_host.data(), H.w_host.size() * 4, hipMemcpyHostToDevice),
-               "copy head");
-    if (!st.good()) return st;
+    if (L.name == "unet.head") {
+      // evaluated by the head kernel in fp32, weights in file layout [3][C][3][3]
+      FFV_TRY(check(hipMalloc(&L.w_dev, L.w_host.size() * 4), "hipMalloc head"));
+      FFV_TRY(check(hipMemcpy(L.w_dev, L.w_host.data(), L.w_host.size() * 4, hipMemcpyHostToDevice),
+                    "copy head"));
+    } else {
+      std::vector<uint8_t> packed = pack_layer(L, dt_);
+      FFV_TRY(check(hipMalloc(&L.w_dev, packed.size()), "hipMalloc weights"));
+      FFV_TRY(check(hipMemcpy(L.w_dev, packed.data(), packed.size(), hipMemcpyHostToDevice),
+                    "copy weights"));
+    }
+    FFV_TRY(check(hipMalloc((void**)&L.b_dev, L.b_host.size() * 4), "hipMalloc bias"));
+    FFV_TRY(check(hipMemcpy(L.b_dev, L.b_host.data(), L.b_host.size() * 4, hipMemcpyHostToDevice),
+                  "copy bias"));
   }
   return Status::ok();
 }
 
-Status Net::make_plan(const Geo& g, int n_cam, int n_view, Plan& p) const {
+CamPlan Net::cam_plan(const Geo& g) const {
   const size_t e = dtype_size(dt_);
   const long P = g.P;
   const int B = base_width_;
-  const size_t A = 256;
+  CamPlan c{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
-    off = align_up(off + bytes, A);
+    off = align_up(off + bytes, 256);
     return o;
   };
-  p.g = g;
-  p.n_cam = n_cam;
-  p.n_view = n_view;
-  const size_t C = n_cam, V = n_view;
-  p.X4 = take(C * P * 4 * 4);
-  p.Xa = take(C * P * 8 * e);
-  p.L0 = take(C * (P / 16) * 4 * 4);
-  p.L1 = take(C * (P / 4) * 4 * 4);
+  c.X4 = take((size_t)P * 4 * 4);
+  c.Xa = take((size_t)P * 8 * e);
+  c.L0 = take((size_t)(P / 16) * 4 * 4);
+  c.L1 = take((size_t)(P / 4) * 4 * 4);
   const int cw[4] = {B / 2, B, 2 * B, 4 * B};
-  for (int k = 0; k < 4; ++k) p.ctx[k] = take(C * (P >> (2 * (k + 1))) * cw[k] * e);
-  p.ctmp = take(C * (P / 4) * (B / 2) * e);
+  for (int k = 0; k < 4; ++k) c.ctx[k] = take((size_t)(P >> (2 * (k + 1))) * cw[k] * e);
+  c.bytes = off;
+  c.ctmp = align_up((size_t)(P / 4) * (B / 2) * e, 256);
+  return c;
+}
+
+CamDev Net::cam_dev(const Geo& g, char* block) const {
+  CamPlan c = cam_plan(g);
+  CamDev d;
+  d.X4 = (const float*)(block + c.X4);
+  d.L0 = (const float*)(block + c.L0);
+  d.L1 = (const float*)(block + c.L1);
+  for (int k = 0; k < 4; ++k) d.ctx[k] = block + c.ctx[k];
+  return d;
+}
+
+ViewPlan Net::view_plan(const Geo& g, int n_view) const {
+  const size_t e = dtype_size(dt_);
+  const long P = g.P;
+  const int B = base_width_;
+  ViewPlan p;
+  p.g = g;
+  p.n_view = n_view;
+  const size_t V = n_view;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
   p.FM[0] = take(V * (P / 16) * 8 * 4);
   p.FM[1] = take(V * (P / 4) * 8 * 4);
   p.FM[2] = take(V * P * 8 * 4);
@@ -354,21 +389,19 @@ Status Net::make_plan(const Geo& g, int n_cam, int n_view, Plan& p) const {
   for (int k = 0; k < 4; ++k) p.Fp[k] = take(V * (P >> (2 * (k + 1))) * 4 * 4);
   p.views = take(V * sizeof(ViewDesc));
   const size_t phase0 = off;
-  // VIBlock region
   p.xin = take(V * P * 24 * e);
   p.a1 = take(V * (P / 4) * 4 * B * e);
   p.bA = take(V * (P / 16) * 8 * B * e);
   p.bB = take(V * (P / 16) * 8 * B * e);
   const size_t end_vib = off;
   off = phase0;
-  // U-Net region (aliases the VIBlock region)
   p.x0u = take(V * P * 24 * e);
   const int lv_ld[4] = {3 * B, 6 * B, 12 * B, 16 * B};
   for (int k = 0; k < 4; ++k) p.lvl[k] = take(V * (P >> (2 * (k + 1))) * lv_ld[k] * e);
   p.etmp = take(V * (P / 4) * B * e);
   p.u4 = take(V * P * (B / 2) * e);
   p.total = std::max(off, end_vib);
-  return Status::ok();
+  return p;
 }
 
 Status Net::ensure_workspace(size_t bytes) {
@@ -379,8 +412,7 @@ Status Net::ensure_workspace(size_t bytes) {
     ws_ = nullptr;
     ws_bytes_ = 0;
   }
-  Status st = check(hipMalloc(&ws_, bytes), "hipMalloc workspace");
-  if (!st.good()) return st;
+  FFV_TRY(check(hipMalloc(&ws_, bytes), "hipMalloc workspace"));
   ws_bytes_ = bytes;
   return Status::ok();
 }
@@ -390,8 +422,8 @@ void Net::set_profiling(bool on) {
   stats_.clear();
 }
 
-void Net::prof_begin() {
-  if (!profiling_) return;
+void Net::prof_begin(const Exec& x) {
+  if (!x.prof) return;
   hipEvent_t e;
   if (!evt_pool_.empty()) {
     e = evt_pool_.back();
@@ -399,12 +431,12 @@ void Net::prof_begin() {
   } else {
     hipEventCreate(&e);
   }
-  hipEventRecord(e, stream_);
+  hipEventRecord(e, x.s);
   cur_start_ = e;
 }
 
-void Net::prof_end(const char* cls, double work) {
-  if (!profiling_ || !cur_start_) return;
+void Net::prof_end(const Exec& x, const char* cls, double work) {
+  if (!x.prof || !cur_start_) return;
   hipEvent_t e;
   if (!evt_pool_.empty()) {
     e = evt_pool_.back();
@@ -412,7 +444,7 @@ void Net::prof_end(const char* cls, double work) {
   } else {
     hipEventCreate(&e);
   }
-  hipEventRecord(e, stream_);
+  hipEventRecord(e, x.s);
   pending_.push_back({cur_start_, e, cls, work});
   cur_start_ = nullptr;
 }
@@ -431,9 +463,9 @@ Status Net::kernel_stats(const std::string& name, long* launches, double* ms, do
   return Status::ok();
 }
 
-Status Net::conv(const Layer& L, const void* in, int in_ld, long in_img_stride, int Hi, int Wi,
-                 int n_img, void* out, int out_ld, long out_img_stride, bool out_f32,
-                 bool accumulate, bool relu) {
+Status Net::conv(const Exec& x, const Layer& L, const void* in, int in_ld, long in_img_stride,
+                 int Hi, int Wi, int n_img, void* out, int out_ld, long out_img_stride,
+                 bool out_f32, bool accumulate, bool relu) {
   ConvArgs a{};
   a.in = in;
   a.in_img_stride = in_img_stride;
@@ -467,6 +499,8 @@ Status Net::conv(const Layer& L, const void* in, int in_ld, long in_img_stride, 
   a.relu = relu ? 1 : 0;
   a.out_f32 = out_f32 ? 1 : 0;
   a.accumulate = accumulate ? 1 : 0;
+  a.taps = L.mode == 1 ? 4 : 9;
+  a.zero = zero_;
   if (in_ld < L.cin_pad || in_ld % 8 != 0) return Status::err(-4, "conv input stride");
   const double flops = 2.0 * n_img * (double)a.Hout * a.Wout * L.cout * L.cin *
                        (L.transposed ? 4.0 : 9.0);
@@ -475,27 +509,209 @@ Status Net::conv(const Layer& L, const void* in, int in_ld, long in_img_stride, 
                                      L.stride == 1)
                                         ? "conv256"
                                         : "conv");
-  prof_begin();
-  Status st = check(launch_conv(dt_, L.tile, a, stream_), L.name.c_str());
-  prof_end(cls, flops);
+  prof_begin(x);
+  Status st = check(launch_conv(dt_, L.tile, a, x.s), L.name.c_str());
+  prof_end(x, cls, flops);
   return st;
 }
 
-#define FFV_TRY(expr)              \
-  do {                             \
-    Status _s = (expr);            \
-    if (!_s.good()) return _s;     \
-  } while (0)
+Status Net::build_cameras(const Exec& x, const Geo& g, const float* const* src_dev, int n_cam,
+                          char* const* blocks, char* ctmp) {
+  if (n_cam <= 0) return Status::ok();
+  const CamPlan c = cam_plan(g);
+  const int B = base_width_;
+  // Camera blocks of one call are contiguous and equally spaced, so every
+  // per-camera pass runs as one batched launch over them.
+  const long stride = blocks[n_cam - 1] - blocks[0];
+  const long cs = n_cam > 1 ? stride / (n_cam - 1) : (long)c.bytes;
+  for (int i = 1; i < n_cam; ++i)
+    if (blocks[i] - blocks[0] != i * cs) return Status::err(-4, "camera blocks not equally spaced");
+  const size_t e = dtype_size(dt_);
+  if (cs % 256 != 0) return Status::err(-4, "camera stride");
+  char* b0 = blocks[0];
+  const long P = g.P;
+  // ingest, padding and the image pyramid, one camera per launch
+  for (int i = 0; i < n_cam; ++i) {
+    prof_begin(x);
+    FFV_TRY(check(launch_ingest(src_dev + i, 1, g.H, g.W, g.Hp, g.Wp, (float*)(blocks[i] + c.X4),
+                                blocks[i] + c.Xa, dt_, x.s),
+                  "ingest"));
+    FFV_TRY(check(launch_resample4((const float*)(blocks[i] + c.X4), 1, g.Hp, g.Wp,
+                                   (float*)(blocks[i] + c.L0), g.Hp / 4, g.Wp / 4, x.s),
+                  "resample L0"));
+    FFV_TRY(check(launch_resample4((const float*)(blocks[i] + c.X4), 1, g.Hp, g.Wp,
+                                   (float*)(blocks[i] + c.L1), g.Hp / 2, g.Wp / 2, x.s),
+                  "resample L1"));
+    prof_end(x, "pixel", (double)g.H * g.W * 12 + P * (16.0 + 8 * e) + 2 * P * 16.0 +
+                             (P / 16 + P / 4) * 16.0);
+  }
+  // ContextNet batched over the cameras: image stride = camera block stride
+  const int cw[4] = {B / 2, B, 2 * B, 4 * B};
+  const char* src = b0 + c.Xa;
+  long src_stride_el = cs / (long)e;
+  int src_ld = 8, h = g.Hp, w = g.Wp;
+  for (int k = 0; k < 4; ++k) {
+    const int ho = h / 2, wo = w / 2;
+    char n1[32], n2[32];
+    snprintf(n1, sizeof n1, "ctx.conv%d", 2 * k + 1);
+    snprintf(n2, sizeof n2, "ctx.conv%d", 2 * k + 2);
+    const long tmp_stride = (long)(c.ctmp / e);
+    FFV_TRY(conv(x, layer(n1), src, src_ld, src_stride_el, h, w, n_cam, ctmp, cw[k], tmp_stride, false,
+                 false, true));
+    FFV_TRY(conv(x, layer(n2), ctmp, cw[k], tmp_stride, ho, wo, n_cam, b0 + c.ctx[k], cw[k],
+                 src_stride_el, false, false, true));
+    src = b0 + c.ctx[k];
+    src_ld = cw[k];
+    h = ho;
+    w = wo;
+  }
+  return Status::ok();
+}
+
+Status Net::run_views(const Exec& x, const ViewPlan& p, const CamDev* cams,
+                      const ViewDesc* views_host, int nv) {
+  const Geo& g = p.g;
+  const long P = g.P;
+  const int B = base_width_;
+  const size_t e = dtype_size(dt_);
+  ViewDesc* views = (ViewDesc*)x.at(p.views);
+  FFV_TRY(check(hipMemcpyAsync(views, views_host, sizeof(ViewDesc) * nv, hipMemcpyHostToDevice, x.s),
+                "copy views"));
+  const int tp = t_plane_ ? 1 : 0;
+
+  // stage 0 input
+  const int h0 = g.Hp / 4, w0 = g.Wp / 4;
+  prof_begin(x);
+  FFV_TRY(check(launch_assemble0(views, nv, cams, h0, w0, x.at(p.xin), 8, dt_, tp, x.s), "assemble0"));
+  prof_end(x, "pixel", (double)nv * (P / 16) * (32.0 + 8 * e));
+
+  for (int s = 0; s < 3; ++s) {
+    const int h = g.Hp * (1 << s) / 4, w = g.Wp * (1 << s) / 4;
+    const long Ps = (long)h * w;
+    const int in_ld = s == 0 ? 8 : 24;
+    char nm[32];
+    auto L = [&](const char* suffix) -> const Layer& {
+      snprintf(nm, sizeof nm, "vib%d.%s", s, suffix);
+      return layer(nm);
+    };
+    if (s > 0) {
+      prof_begin(x);
+      FFV_TRY(check(launch_transition(views, nv, cams, s, (const float*)x.at(p.FM[s - 1]), h / 2, w / 2,
+                                      h, w, x.at(p.xin), 24, (float*)x.at(p.FM[s]), dt_, tp, x.s),
+                    "transition"));
+      prof_end(x, "pixel", (double)nv * Ps * (20.0 / 4 + 16 * 4 + 24 * e + 32));
+    }
+    const int h1 = h / 2, w1 = w / 2, h2 = h / 4, w2 = w / 4;
+    const int C1 = 4 * B, C2 = 8 * B;
+    FFV_TRY(conv(x, L("conv1"), x.at(p.xin), in_ld, Ps * in_ld, h, w, nv, x.at(p.a1), C1,
+                 (long)h1 * w1 * C1, false, false, true));
+    FFV_TRY(conv(x, L("conv2"), x.at(p.a1), C1, (long)h1 * w1 * C1, h1, w1, nv, x.at(p.bA), C2,
+                 (long)h2 * w2 * C2, false, false, true));
+    void* cur = x.at(p.bA);
+    void* nxt = x.at(p.bB);
+    for (int i = 3; i <= 8; ++i) {
+      char suf[16];
+      snprintf(suf, sizeof suf, "conv%d", i);
+      FFV_TRY(conv(x, L(suf), cur, C2, (long)h2 * w2 * C2, h2, w2, nv, nxt, C2, (long)h2 * w2 * C2,
+                   false, false, true));
+      std::swap(cur, nxt);
+    }
+    FFV_TRY(conv(x, L("convT1"), cur, C2, (long)h2 * w2 * C2, h2, w2, nv, x.at(p.a1), C1,
+                 (long)h1 * w1 * C1, false, false, true));
+    FFV_TRY(conv(x, L("convT2"), x.at(p.a1), C1, (long)h1 * w1 * C1, h1, w1, nv, x.at(p.FM[s]), 8,
+                 Ps * 8, true, s > 0, false));
+  }
+
+  // final warp + blend, U-Net input
+  prof_begin(x);
+  FFV_TRY(check(launch_final(views, nv, cams, (const float*)x.at(p.FM[2]), g.Hp, g.Wp,
+                             (float*)x.at(p.I2), x.at(p.x0u), 24, dt_, x.s),
+                "final"));
+  prof_end(x, "pixel", (double)nv * P * (20.0 + 16 * 4 + 16 + 24 * e));
+
+  // flow pyramid and context warps
+  {
+    const float* src = (const float*)x.at(p.FM[2]);
+    int ld = 8, h = g.Hp, w = g.Wp;
+    const int cw[4] = {B / 2, B, 2 * B, 4 * B};
+    const int lv_ld[4] = {3 * B, 6 * B, 12 * B, 16 * B};
+    const int lv_off[4] = {2 * B, 4 * B, 8 * B, 8 * B};
+    for (int k = 0; k < 4; ++k) {
+      const int ho = h / 2, wo = w / 2;
+      const long Pk = (long)ho * wo;
+      prof_begin(x);
+      FFV_TRY(check(launch_flow_down(src, ld, nv, h, w, (float*)x.at(p.Fp[k]), x.s), "flow_down"));
+      FFV_TRY(check(launch_ctx_warp(views, nv, cams, k, cw[k], (const float*)x.at(p.Fp[k]), ho, wo,
+                                    x.at(p.lvl[k]) + lv_off[k] * e, lv_ld[k], Pk * lv_ld[k], dt_, x.s),
+                    "ctx_warp"));
+      prof_end(x, "pixel", (double)nv * ((double)h * w * 16 + Pk * 16 + 2 * Pk * 16 +
+                                         2.0 * Pk * cw[k] * e * 2));
+      src = (const float*)x.at(p.Fp[k]);
+      ld = 4;
+      h = ho;
+      w = wo;
+    }
+  }
+
+  // context-aware U-Net
+  {
+    const int ew[4] = {B, 2 * B, 4 * B, 8 * B};
+    const int lv_ld[4] = {3 * B, 6 * B, 12 * B, 16 * B};
+    const void* src = x.at(p.x0u);
+    int src_ld = 24, h = g.Hp, w = g.Wp;
+    for (int k = 0; k < 4; ++k) {
+      const int ho = h / 2, wo = w / 2;
+      char n1[32], n2[32];
+      snprintf(n1, sizeof n1, "unet.enc%d", 2 * k + 1);
+      snprintf(n2, sizeof n2, "unet.enc%d", 2 * k + 2);
+      FFV_TRY(conv(x, layer(n1), src, src_ld, (long)h * w * src_ld, h, w, nv, x.at(p.etmp), ew[k],
+                   (long)ho * wo * ew[k], false, false, true));
+      // level buffer k holds [u | d | wc_l | wc_r]; d_{k+1} follows the decoder slot
+      const int d_off = k < 3 ? ew[k] : 0;
+      char* dst = x.at(p.lvl[k]) + (size_t)d_off * e;
+      FFV_TRY(conv(x, layer(n2), x.at(p.etmp), ew[k], (long)ho * wo * ew[k], ho, wo, nv, dst, lv_ld[k],
+                   (long)ho * wo * lv_ld[k], false, false, true));
+      src = dst;
+      src_ld = lv_ld[k];
+      h = ho;
+      w = wo;
+    }
+    for (int k = 0; k < 4; ++k) {
+      const int lvl_in = 3 - k;
+      const int hi = g.Hp >> (lvl_in + 1), wi = g.Wp >> (lvl_in + 1);
+      char nm[32];
+      snprintf(nm, sizeof nm, "unet.dec%d", k + 1);
+      void* dst;
+      int dst_ld;
+      if (k < 3) {
+        dst = x.at(p.lvl[lvl_in - 1]);
+        dst_ld = lv_ld[lvl_in - 1];
+      } else {
+        dst = x.at(p.u4);
+        dst_ld = B / 2;
+      }
+      FFV_TRY(conv(x, layer(nm), x.at(p.lvl[lvl_in]), lv_ld[lvl_in], (long)hi * wi * lv_ld[lvl_in], hi,
+                   wi, nv, dst, dst_ld, (long)(2 * hi) * (2 * wi) * dst_ld, false, false, true));
+    }
+  }
+
+  // output head
+  {
+    const Layer& Hd = layer("unet.head");
+    prof_begin(x);
+    FFV_TRY(check(launch_head(x.at(p.u4), B / 2, B / 2, (const float*)Hd.w_dev, Hd.b_dev,
+                              (const float*)x.at(p.I2), views, nv, g.Hp, g.Wp, g.H, g.W, dt_, x.s),
+                  "head"));
+    prof_end(x, "head", (double)nv * ((double)P * (B / 2) * e + (double)P * 16 + 12.0 * g.H * g.W));
+  }
+  return Status::ok();
+}
 
 Status Net::interpolate(const float* const* left, const float* const* right, int n_pairs, int H,
                         int W, const float* t, int n_t, float* out) {
+  std::lock_guard<std::mutex> lk(call_mu_);
   FFV_TRY(check(hipSetDevice(device_), "hipSetDevice"));
-  Geo g;
-  g.H = H;
-  g.W = W;
-  g.Hp = round_up(H, 16);
-  g.Wp = round_up(W, 16);
-  g.P = (long)g.Hp * g.Wp;
+  const Geo g = Geo::of(H, W);
 
   // distinct cameras
   std::vector<const float*> cams;
@@ -513,84 +729,61 @@ Status Net::interpolate(const float* const* left, const float* const* right, int
   const int n_cam = (int)cams.size();
   const int n_view_total = n_pairs * n_t;
 
-  // chunk size: as many views as fit the workspace cap
-  Plan one;
-  FFV_TRY(make_plan(g, n_cam, 1, one));
-  Plan two;
-  FFV_TRY(make_plan(g, n_cam, 2, two));
-  const size_t per_view = two.total - one.total;
-  const size_t fixed = one.total - per_view;
+  // workspace: [camera blocks][camera scratch][camera table + image table][views]
+  const CamPlan cp = cam_plan(g);
+  const size_t cam_region = align_up(cp.bytes * n_cam, 256);
+  const size_t ctmp_region = align_up(cp.ctmp * n_cam, 256);
+  const size_t tab_region = align_up(sizeof(CamDev) * n_cam + sizeof(void*) * n_cam, 256);
+  const size_t fixed = cam_region + ctmp_region + tab_region;
+  const size_t per_view = view_plan(g, 2).total - view_plan(g, 1).total;
   int chunk = n_view_total;
-  if (!debug_ && fixed + per_view * (size_t)chunk > ws_cap_) {
-    chunk = (int)std::max<size_t>(1, (ws_cap_ > fixed ? (ws_cap_ - fixed) / per_view : 1));
-  }
-  chunk = std::min(chunk, n_view_total);
-  Plan p;
-  FFV_TRY(make_plan(g, n_cam, chunk, p));
-  FFV_TRY(ensure_workspace(p.total));
+  if (!debug_ && fixed + view_plan(g, chunk).total > ws_cap_)
+    chunk = (int)std::max<size_t>(1, ws_cap_ > fixed + per_view ? (ws_cap_ - fixed) / per_view : 1);
+  chunk = std::max(1, std::min(chunk, n_view_total));
+  while (chunk > 1 && fixed + view_plan(g, chunk).total > ws_cap_) --chunk;
+  const ViewPlan vp = view_plan(g, chunk);
+  FFV_TRY(ensure_workspace(fixed + vp.total));
 
-  // camera pointer table
-  if (src_ptrs_cap_ < (size_t)n_cam) {
-    if (src_ptrs_) hipFree(src_ptrs_);
-    src_ptrs_ = nullptr;
-    FFV_TRY(check(hipMalloc(&src_ptrs_, sizeof(void*) * n_cam), "hipMalloc ptrs"));
-    src_ptrs_cap_ = n_cam;
+  char* base = (char*)ws_;
+  Exec x;
+  x.s = stream_;
+  x.prof = profiling_;
+  std::vector<char*> blocks(n_cam);
+  std::vector<CamDev> camdev(n_cam);
+  for (int i = 0; i < n_cam; ++i) {
+    blocks[i] = base + cp.bytes * i;
+    camdev[i] = cam_dev(g, blocks[i]);
   }
-  FFV_TRY(check(hipMemcpyAsync(src_ptrs_, cams.data(), sizeof(void*) * n_cam, hipMemcpyHostToDevice,
+  char* ctmp = base + cam_region;
+  CamDev* cam_tab = (CamDev*)(base + cam_region + ctmp_region);
+  const float** src_tab = (const float**)((char*)cam_tab + sizeof(CamDev) * n_cam);
+  FFV_TRY(check(hipMemcpyAsync(cam_tab, camdev.data(), sizeof(CamDev) * n_cam, hipMemcpyHostToDevice,
                                stream_),
-                "copy ptrs"));
+                "copy camera table"));
+  FFV_TRY(check(hipMemcpyAsync(src_tab, cams.data(), sizeof(void*) * n_cam, hipMemcpyHostToDevice,
+                               stream_),
+                "copy image table"));
+  FFV_TRY(build_cameras(x, g, src_tab, n_cam, blocks.data(), ctmp));
 
-  const long P = g.P;
-  const int B = base_width_;
-  const size_t e = dtype_size(dt_);
-  float* X4 = (float*)ws(p.X4);
-  // 1. ingest + pad, image pyramid
-  prof_begin();
-  FFV_TRY(check(launch_ingest((const float* const*)src_ptrs_, n_cam, H, W, g.Hp, g.Wp, X4, ws(p.Xa),
-                              dt_, stream_),
-                "ingest"));
-  prof_end("pixel", (double)n_cam * (H * (double)W * 12 + P * (16.0 + 8 * e)));
-  prof_begin();
-  FFV_TRY(check(launch_resample4(X4, n_cam, g.Hp, g.Wp, (float*)ws(p.L0), g.Hp / 4, g.Wp / 4, stream_),
-                "resample L0"));
-  FFV_TRY(check(launch_resample4(X4, n_cam, g.Hp, g.Wp, (float*)ws(p.L1), g.Hp / 2, g.Wp / 2, stream_),
-                "resample L1"));
-  prof_end("pixel", (double)n_cam * (2 * P * 16.0 + (P / 16 + P / 4) * 16.0));
-
-  // 2. ContextNet over all cameras
-  {
-    const int cw[4] = {B / 2, B, 2 * B, 4 * B};
-    const void* src = ws(p.Xa);
-    int src_ld = 8, h = g.Hp, w = g.Wp;
-    for (int k = 0; k < 4; ++k) {
-      const int ho = h / 2, wo = w / 2;
-      char n1[32], n2[32];
-      snprintf(n1, sizeof n1, "ctx.conv%d", 2 * k + 1);
-      snprintf(n2, sizeof n2, "ctx.conv%d", 2 * k + 2);
-      FFV_TRY(conv(layer(n1), src, src_ld, (long)h * w * src_ld, h, w, n_cam, ws(p.ctmp), cw[k],
-                   (long)ho * wo * cw[k], false, false, true));
-      FFV_TRY(conv(layer(n2), ws(p.ctmp), cw[k], (long)ho * wo * cw[k], ho, wo, n_cam, ws(p.ctx[k]),
-                   cw[k], (long)ho * wo * cw[k], false, false, true));
-      src = ws(p.ctx[k]);
-      src_ld = cw[k];
-      h = ho;
-      w = wo;
-    }
-  }
-
-  // 3. views, in chunks
   std::vector<ViewDesc> vd(n_view_total);
   for (int i = 0; i < n_pairs; ++i)
-    for (int j = 0; j < n_t; ++j) vd[(size_t)i * n_t + j] = {li[i], ri[i], t[j], 0};
-  std::vector<float*> outs(n_view_total);
-  for (int v = 0; v < n_view_total; ++v) outs[v] = out + (size_t)v * 3 * H * W;
+    for (int j = 0; j < n_t; ++j) {
+      ViewDesc& d = vd[(size_t)i * n_t + j];
+      d = ViewDesc{};
+      d.cam_l = li[i];
+      d.cam_r = ri[i];
+      d.t = t[j];
+      d.out = out + ((size_t)i * n_t + j) * 3 * (size_t)H * W;
+    }
+  Exec xv = x;
+  xv.ws = base + fixed;
   for (int v0 = 0; v0 < n_view_total; v0 += chunk) {
     const int nv = std::min(chunk, n_view_total - v0);
-    FFV_TRY(run_chunk(p, vd.data() + v0, nv, outs.data() + v0));
+    FFV_TRY(run_views(xv, vp, cam_tab, vd.data() + v0, nv));
   }
-  (void)e;
   FFV_TRY(check(hipStreamSynchronize(stream_), "hipStreamSynchronize"));
-  last_plan_ = p;
+  last_plan_ = vp;
+  last_views_ws_ = xv.ws;
   have_taps_ = true;
   if (profiling_) {
     for (auto& pe : pending_) {
@@ -608,180 +801,24 @@ Status Net::interpolate(const float* const* left, const float* const* right, int
   return Status::ok();
 }
 
-Status Net::run_chunk(const Plan& p, const ViewDesc* views_host, int nv, float* const* outs) {
-  const Geo& g = p.g;
-  const long P = g.P;
-  const int B = base_width_;
-  const size_t e = dtype_size(dt_);
-  ViewDesc* views = (ViewDesc*)ws(p.views);
-  FFV_TRY(check(hipMemcpyAsync(views, views_host, sizeof(ViewDesc) * nv, hipMemcpyHostToDevice,
-                               stream_),
-                "copy views"));
-  const int tp = t_plane_ ? 1 : 0;
-
-  // stage 0 input
-  const int h0 = g.Hp / 4, w0 = g.Wp / 4;
-  prof_begin();
-  FFV_TRY(check(launch_assemble0(views, nv, (const float*)ws(p.L0), (P / 16) * 4, h0, w0, ws(p.xin), 8,
-                                 dt_, tp, stream_),
-                "assemble0"));
-  prof_end("pixel", (double)nv * (P / 16) * (32.0 + 8 * e));
-
-  for (int s = 0; s < 3; ++s) {
-    const int h = g.Hp * (1 << s) / 4, w = g.Wp * (1 << s) / 4;
-    const long Ps = (long)h * w;
-    const int in_ld = s == 0 ? 8 : 24;
-    char nm[32];
-    auto L = [&](const char* suffix) -> const Layer& {
-      snprintf(nm, sizeof nm, "vib%d.%s", s, suffix);
-      return layer(nm);
-    };
-    if (s > 0) {
-      const int hp = h / 2, wp = w / 2;
-      const float* Limg = s == 1 ? (const float*)ws(p.L1) : (const float*)ws(p.X4);
-      const long cam_stride = s == 1 ? (P / 4) * 4 : P * 4;
-      prof_begin();
-      FFV_TRY(check(launch_transition(views, nv, (const float*)ws(p.FM[s - 1]), hp, wp, Limg,
-                                      cam_stride, h, w, ws(p.xin), 24, (float*)ws(p.FM[s]), dt_, tp,
-                                      stream_),
-                    "transition"));
-      prof_end("pixel", (double)nv * Ps * (20.0 / 4 + 16 * 4 + 24 * e + 32));
-    }
-    // VIBlock_s
-    const int h1 = h / 2, w1 = w / 2, h2 = h / 4, w2 = w / 4;
-    const int C1 = 4 * B, C2 = 8 * B;
-    FFV_TRY(conv(L("conv1"), ws(p.xin), in_ld, Ps * in_ld, h, w, nv, ws(p.a1), C1, (long)h1 * w1 * C1,
-                 false, false, true));
-    FFV_TRY(conv(L("conv2"), ws(p.a1), C1, (long)h1 * w1 * C1, h1, w1, nv, ws(p.bA), C2,
-                 (long)h2 * w2 * C2, false, false, true));
-    void* cur = ws(p.bA);
-    void* nxt = ws(p.bB);
-    for (int i = 3; i <= 8; ++i) {
-      char suf[16];
-      snprintf(suf, sizeof suf, "conv%d", i);
-      FFV_TRY(conv(L(suf), cur, C2, (long)h2 * w2 * C2, h2, w2, nv, nxt, C2, (long)h2 * w2 * C2, false,
-                   false, true));
-      std::swap(cur, nxt);
-    }
-    FFV_TRY(conv(L("convT1"), cur, C2, (long)h2 * w2 * C2, h2, w2, nv, ws(p.a1), C1, (long)h1 * w1 * C1,
-                 false, false, true));
-    FFV_TRY(conv(L("convT2"), ws(p.a1), C1, (long)h1 * w1 * C1, h1, w1, nv, ws(p.FM[s]), 8, Ps * 8, true,
-                 s > 0, false));
-  }
-
-  // final warp + blend, U-Net input
-  prof_begin();
-  FFV_TRY(check(launch_final(views, nv, (const float*)ws(p.FM[2]), (const float*)ws(p.X4), P * 4,
-                             g.Hp, g.Wp, (float*)ws(p.I2), ws(p.x0u), 24, dt_, stream_),
-                "final"));
-  prof_end("pixel", (double)nv * P * (20.0 + 16 * 4 + 16 + 24 * e));
-
-  // flow pyramid and context warps
-  {
-    const float* src = (const float*)ws(p.FM[2]);
-    int ld = 8, h = g.Hp, w = g.Wp;
-    const int cw[4] = {B / 2, B, 2 * B, 4 * B};
-    const int lv_ld[4] = {3 * B, 6 * B, 12 * B, 16 * B};
-    const int lv_off[4] = {2 * B, 4 * B, 8 * B, 8 * B};
-    for (int k = 0; k < 4; ++k) {
-      const int ho = h / 2, wo = w / 2;
-      const long Pk = (long)ho * wo;
-      prof_begin();
-      FFV_TRY(check(launch_flow_down(src, ld, nv, h, w, (float*)ws(p.Fp[k]), stream_), "flow_down"));
-      FFV_TRY(check(launch_ctx_warp(views, nv, ws(p.ctx[k]), Pk * cw[k], cw[k], (const float*)ws(p.Fp[k]),
-                                    ho, wo, (char*)ws(p.lvl[k]) + lv_off[k] * e, lv_ld[k],
-                                    Pk * lv_ld[k], dt_, stream_),
-                    "ctx_warp"));
-      prof_end("pixel", (double)nv * ((double)h * w * 16 + Pk * 16 + 2 * Pk * 16 +
-                                      2.0 * Pk * cw[k] * e * 2));
-      src = (const float*)ws(p.Fp[k]);
-      ld = 4;
-      h = ho;
-      w = wo;
-    }
-  }
-
-  // context-aware U-Net
-  {
-    const int ew[4] = {B, 2 * B, 4 * B, 8 * B};
-    const int lv_ld[4] = {3 * B, 6 * B, 12 * B, 16 * B};
-    // encoder: level k reads [d_k, wc_k] (channels [ew[k-1], ...) of lvl[k-1]) or x0u
-    const void* src = ws(p.x0u);
-    int src_ld = 24, h = g.Hp, w = g.Wp;
-    for (int k = 0; k < 4; ++k) {
-      const int ho = h / 2, wo = w / 2;
-      char n1[32], n2[32];
-      snprintf(n1, sizeof n1, "unet.enc%d", 2 * k + 1);
-      snprintf(n2, sizeof n2, "unet.enc%d", 2 * k + 2);
-      FFV_TRY(conv(layer(n1), src, src_ld, (long)h * w * src_ld, h, w, nv, ws(p.etmp), ew[k],
-                   (long)ho * wo * ew[k], false, false, true));
-      // d_{k+1} goes after the decoder slot in lvl[k] (offset ew[k] for k < 3, 0 for the deepest)
-      const int d_off = k < 3 ? ew[k] : 0;
-      char* dst = (char*)ws(p.lvl[k]) + (size_t)d_off * e;
-      FFV_TRY(conv(layer(n2), ws(p.etmp), ew[k], (long)ho * wo * ew[k], ho, wo, nv, dst, lv_ld[k],
-                   (long)ho * wo * lv_ld[k], false, false, true));
-      src = dst;
-      src_ld = lv_ld[k];
-      h = ho;
-      w = wo;
-    }
-    // decoder
-    const int dout[4] = {4 * B, 2 * B, B, B / 2};
-    for (int k = 0; k < 4; ++k) {
-      const int lvl_in = 3 - k;  // lvl[3] .. lvl[0]
-      const int hi = g.Hp >> (lvl_in + 1), wi = g.Wp >> (lvl_in + 1);
-      const void* in = ws(p.lvl[lvl_in]);
-      char nm[32];
-      snprintf(nm, sizeof nm, "unet.dec%d", k + 1);
-      void* dst;
-      int dst_ld;
-      long dst_stride;
-      if (k < 3) {
-        dst = ws(p.lvl[lvl_in - 1]);
-        dst_ld = lv_ld[lvl_in - 1];
-      } else {
-        dst = ws(p.u4);
-        dst_ld = B / 2;
-      }
-      dst_stride = (long)(2 * hi) * (2 * wi) * dst_ld;
-      (void)dout;
-      FFV_TRY(conv(layer(nm), in, lv_ld[lvl_in], (long)hi * wi * lv_ld[lvl_in], hi, wi, nv, dst, dst_ld,
-                   dst_stride, false, false, true));
-    }
-  }
-
-  // output head
-  {
-    const Layer& Hd = layer("unet.head");
-    // outputs of a chunk are contiguous when the chunk's views are
-    float* o = outs[0];
-    prof_begin();
-    FFV_TRY(check(launch_head(ws(p.u4), B / 2, B / 2, (const float*)Hd.w_dev, Hd.b_dev, (const float*)ws(p.I2),
-                              nv, g.Hp, g.Wp, g.H, g.W, o, dt_, stream_),
-                  "head"));
-    prof_end("head", (double)nv * ((double)P * (B / 2) * e + (double)P * 16 + 12.0 * g.H * g.W));
-  }
-  return Status::ok();
-}
-
 Status Net::debug_tap(const std::string& name, float* dst, size_t cap, int dims[3]) {
+  std::lock_guard<std::mutex> lk(call_mu_);
   if (!have_taps_) return Status::err(-7, "no forward pass recorded");
-  const Plan& p = last_plan_;
+  const ViewPlan& p = last_plan_;
   const Geo& g = p.g;
-  const void* src;
+  const char* src;
   int C, ld, h, w;
-  DType dt = DType::F32;
   if (name == "F0" || name == "F1" || name == "F2") {
     const int s = name[1] - '0';
     h = g.Hp * (1 << s) / 4;
     w = g.Wp * (1 << s) / 4;
-    src = ws(p.FM[s]);
+    src = last_views_ws_ + p.FM[s];
     C = 5;
     ld = 8;
   } else if (name == "I2") {
     h = g.Hp;
     w = g.Wp;
-    src = ws(p.I2);
+    src = last_views_ws_ + p.I2;
     C = 3;
     ld = 4;
   } else {
@@ -792,8 +829,16 @@ Status Net::debug_tap(const std::string& name, float* dst, size_t cap, int dims[
   dims[0] = C;
   dims[1] = h;
   dims[2] = w;
-  FFV_TRY(check(launch_extract(src, dt, ld, C, (long)h * w, dst, stream_), "extract"));
+  FFV_TRY(check(launch_extract(src, DType::F32, ld, C, (long)h * w, dst, stream_), "extract"));
   return check(hipStreamSynchronize(stream_), "sync");
+}
+
+Status Net::start_serving(size_t budget, float tick_ms, int max_batch_views) {
+  if (server_) return Status::err(-7, "serving already started");
+  server_.reset(new Server(this, budget, tick_ms, max_batch_views));
+  Status st = server_->start();
+  if (!st.good()) server_.reset();
+  return st;
 }
 
 }  // namespace ffv

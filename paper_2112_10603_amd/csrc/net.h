@@ -1,9 +1,16 @@
 // Network executor: weights, packed per precision; workspace planning; the
-// forward launch sequence of the view-interpolation network.
+// forward launch sequence of the view-interpolation network; the serving
+// scheduler.
 #pragma once
 
+#include <atomic>
+#include <condition_variable>
+#include <deque>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -57,6 +64,41 @@ struct KernelStat {
   double work = 0.0;
 };
 
+// Image geometry: real size and the size padded to a multiple of 16.
+struct Geo {
+  int H = 0, W = 0, Hp = 0, Wp = 0;
+  long P = 0;
+  static Geo of(int H, int W);
+  bool operator==(const Geo& o) const { return H == o.H && W == o.W; }
+};
+
+// Where kernels run: a stream and the base of a workspace.
+struct Exec {
+  hipStream_t s = nullptr;
+  char* ws = nullptr;
+  bool prof = false;
+  char* at(size_t off) const { return ws + off; }
+};
+
+// Byte offsets of one camera's resident data inside a camera block.
+struct CamPlan {
+  size_t X4, Xa, L0, L1, ctx[4];
+  size_t bytes;  // one camera block
+  size_t ctmp;   // scratch per camera while building (context convs)
+};
+
+// Byte offsets of one chunk of views inside a view workspace.
+struct ViewPlan {
+  Geo g;
+  int n_view = 0;
+  size_t FM[3], I2, Fp[4], views;
+  size_t xin, a1, bA, bB;          // VIBlocks
+  size_t x0u, lvl[4], etmp, u4;    // U-Net (aliases the VIBlock buffers)
+  size_t total = 0;
+};
+
+class Server;
+
 class Net {
  public:
   Net() = default;
@@ -73,36 +115,32 @@ class Net {
   int device() const { return device_; }
   hipStream_t stream() const { return stream_; }
 
- private:
-  struct Geo {
-    int H = 0, W = 0, Hp = 0, Wp = 0;
-    long P = 0;
-  };
-  // Byte offsets of every buffer in the workspace for one geometry.
-  struct Plan {
-    Geo g;
-    int n_cam = 0, n_view = 0;
-    size_t total = 0;
-    // camera region
-    size_t X4, Xa, L0, L1, ctx[4], ctmp;
-    // view region
-    size_t FM[3], I2, Fp[4], views;
-    // aliased phase region
-    size_t xin, a1, bA, bB;                          // VIBlocks
-    size_t x0u, lvl[4], etmp, u4;                    // U-Net
-  };
+  // serving
+  Status start_serving(size_t budget, float tick_ms, int max_batch_views);
+  Server* server() { return server_.get(); }
 
-  Status make_plan(const Geo& g, int n_cam, int n_view, Plan& p) const;
+  // building blocks (also used by the server)
+  CamPlan cam_plan(const Geo& g) const;
+  ViewPlan view_plan(const Geo& g, int n_view) const;
+  // Build n_cam cameras' resident data: src is a device table of n_cam
+  // planar [3][H][W] images; camera i's block starts at blocks[i] (host
+  // array of device pointers). ctmp is scratch of n_cam * cp.ctmp bytes.
+  Status build_cameras(const Exec& x, const Geo& g, const float* const* src_dev, int n_cam,
+                       char* const* blocks, char* ctmp);
+  // Run nv views (descriptors on the host, copied to the plan's view slot).
+  Status run_views(const Exec& x, const ViewPlan& p, const CamDev* cams_dev,
+                   const ViewDesc* views_host, int nv);
+  CamDev cam_dev(const Geo& g, char* block) const;
+  Status check(hipError_t e, const char* what) const;
+
+ private:
   Status ensure_workspace(size_t bytes);
-  Status run_chunk(const Plan& p, const ViewDesc* views_host, int n_view, float* const* outs);
-  Status conv(const Layer& L, const void* in, int in_ld, long in_img_stride, int Hi, int Wi,
-              int n_img, void* out, int out_ld, long out_img_stride, bool out_f32, bool accumulate,
-              bool relu);
+  Status conv(const Exec& x, const Layer& L, const void* in, int in_ld, long in_img_stride, int Hi,
+              int Wi, int n_img, void* out, int out_ld, long out_img_stride, bool out_f32,
+              bool accumulate, bool relu);
   const Layer& layer(const std::string& n) const { return layers_.at(n); }
-  char* ws(size_t off) const { return static_cast<char*>(ws_) + off; }
-  void prof_begin();
-  void prof_end(const char* cls, double work);
-  Status check(hipError_t e, const char* what);
+  void prof_begin(const Exec& x);
+  void prof_end(const Exec& x, const char* cls, double work);
 
   std::map<std::string, Layer> layers_;
   int base_width_ = 32;
@@ -114,11 +152,12 @@ class Net {
   size_t ws_cap_ = 0;
   void* ws_ = nullptr;
   size_t ws_bytes_ = 0;
-  void* src_ptrs_ = nullptr;  // device array of camera image pointers
-  size_t src_ptrs_cap_ = 0;
+  void* zero_ = nullptr;      // 256 zero bytes read by convs for taps outside the image
   bool debug_ = false;
   bool have_taps_ = false;
-  Plan last_plan_{};
+  ViewPlan last_plan_{};
+  char* last_views_ws_ = nullptr;
+  std::mutex call_mu_;        // serialises interpolate() per net
 
   bool profiling_ = false;
   struct PendingEvt {
@@ -130,6 +169,93 @@ class Net {
   std::vector<hipEvent_t> evt_pool_;
   hipEvent_t cur_start_ = nullptr;
   std::map<std::string, KernelStat> stats_;
+
+  std::unique_ptr<Server> server_;
 };
+
+// ----------------------------------------------------------------------
+// Serving: cameras registered once (resident image pyramid and context
+// features), requests (camera pair, t, output) submitted from any thread,
+// batched per tick under an HBM admission budget, each batch run on a slot
+// (stream + workspace) of its own so consecutive batches overlap on the
+// device.
+
+struct Request {
+  int cam_l = 0, cam_r = 0;
+  float t = 0.f;
+  float* out = nullptr;
+  uint64_t tag = 0;
+};
+
+struct Timing {
+  double t_submit = 0, t_admit = 0, t_launch = 0, t_done = 0;
+};
+
+class Server {
+ public:
+  static constexpr int kMaxCams = 1024;
+  Server(Net* net, size_t budget, float tick_ms, int max_batch_views);
+  ~Server();
+  Status start();
+  Status register_camera(int cam_id, const float* image, int H, int W);
+  Status submit(const Request& r, uint64_t* ticket);
+  // done = true with the timing when finished (the ticket is then
+  // collected); done = false while queued or running.
+  Status poll(uint64_t ticket, Timing* timing, bool* done);
+  Status stats(long* admitted, long* completed, long* queued, size_t* bytes_in_use);
+
+ private:
+  struct Camera {
+    Geo g;
+    char* block = nullptr;
+    int slot = -1;  // index into the device camera table
+  };
+  struct Ticket {
+    Request req;
+    Geo g;
+    Timing tm;
+    // 0 queued, 1 admitted, 2 done; set to 2 by the completion callback
+    // (release) after tm.t_done, without the scheduler lock
+    std::atomic<int> state{0};
+  };
+  struct Slot {
+    hipStream_t s = nullptr;
+    char* ws = nullptr;
+    size_t bytes = 0;
+    std::atomic<bool> busy{false};
+    std::vector<Ticket*> tickets;  // written before launch, read by the callback
+  };
+  struct Done {
+    Server* srv;
+    Slot* slot;  // stable: slots are never moved or freed while serving
+  };
+  static void on_done(void* p);
+  void loop();
+  void admit_and_launch();  // called with mu_ held
+  size_t view_bytes(const Geo& g, int n) const;
+
+  Net* net_;
+  size_t budget_;
+  float tick_ms_;
+  int max_batch_;
+  std::thread thr_;
+  std::mutex mu_;
+  std::condition_variable cv_;
+  bool stop_ = false;
+  std::map<int, Camera> cams_;
+  std::vector<int> free_cam_slots_;
+  CamDev* cam_table_ = nullptr;  // device table, kMaxCams entries
+  size_t resident_bytes_ = 0;
+  size_t slot_bytes_ = 0;
+  std::deque<uint64_t> queue_;
+  std::map<uint64_t, Ticket> tickets_;  // nodes are stable: callbacks hold Ticket*
+  uint64_t next_ticket_ = 1;
+  std::vector<std::unique_ptr<Slot>> slots_;
+  std::vector<std::unique_ptr<Done>> done_ctx_;
+  long n_admitted_ = 0;
+  std::atomic<long> n_completed_{0};
+};
+
+double now_seconds();
 
 }  // namespace ffv

@@ -113,15 +113,15 @@ __global__ void resample4_k(const float* in, int Hi, int Wi, float* out, int Ho,
 
 // ------------------------------------------------------ stage-0 input
 template <typename T>
-__global__ void assemble0_k(const ViewDesc* views, const float* L0, long cam_stride, int h, int w,
-                            T* x, int ld, int t_plane) {
+__global__ void assemble0_k(const ViewDesc* views, const CamDev* cams, int h, int w, T* x, int ld,
+                            int t_plane) {
   const int v = blockIdx.y;
   const long P = (long)h * w;
   const long p = (long)blockIdx.x * TPB + threadIdx.x;
   if (p >= P) return;
   const ViewDesc d = views[v];
-  const float4 l = ld4(L0 + d.cam_l * cam_stride + 4 * p);
-  const float4 r = ld4(L0 + d.cam_r * cam_stride + 4 * p);
+  const float4 l = ld4(cams[d.cam_l].L0 + 4 * p);
+  const float4 r = ld4(cams[d.cam_r].L0 + 4 * p);
   T* o = x + ((long)v * P + p) * ld;
   o[0] = cvt<T>(l.x);
   o[1] = cvt<T>(l.y);
@@ -136,8 +136,8 @@ __global__ void assemble0_k(const ViewDesc* views, const float* L0, long cam_str
 // ---------------------------------------- stage transition s -> s+1 (Eq. 2)
 // FM layout: 8 floats per pixel = (F_l.x, F_l.y, F_r.x, F_r.y, M, 0, 0, 0).
 template <typename T>
-__global__ void transition_k(const ViewDesc* views, const float* FMprev, int hp, int wp,
-                             const float* Limg, long cam_stride, int h, int w, T* x, int ld,
+__global__ void transition_k(const ViewDesc* views, const CamDev* cams, int level,
+                             const float* FMprev, int hp, int wp, int h, int w, T* x, int ld,
                              float* FM, int t_plane) {
   const int v = blockIdx.y;
   const long P = (long)h * w;
@@ -160,8 +160,8 @@ __global__ void transition_k(const ViewDesc* views, const float* FMprev, int hp,
     up[c] = (q00[c] * (1.f - ax) + q01[c] * ax) * (1.f - by) + (q10[c] * (1.f - ax) + q11[c] * ax) * by;
   const float Fx = 2.f * up[0], Fy = 2.f * up[1], Gx = 2.f * up[2], Gy = 2.f * up[3], Mt = up[4];
 
-  const float* Lc = Limg + d.cam_l * cam_stride;
-  const float* Rc = Limg + d.cam_r * cam_stride;
+  const float* Lc = level == 1 ? cams[d.cam_l].L1 : cams[d.cam_l].X4;
+  const float* Rc = level == 1 ? cams[d.cam_r].L1 : cams[d.cam_r].X4;
   const float4 L = ld4(Lc + 4 * p), R = ld4(Rc + 4 * p);
   const float4 Wl = sample4(Lc, warp_taps(xx, y, Fx, Fy, w, h));
   const float4 Wr = sample4(Rc, warp_taps(xx, y, Gx, Gy, w, h));
@@ -179,8 +179,8 @@ __global__ void transition_k(const ViewDesc* views, const float* FMprev, int hp,
 
 // ------------------------------------ final warp + mask blend (Eq. 1)
 template <typename T>
-__global__ void final_k(const ViewDesc* views, const float* FM, const float* X4, long cam_stride,
-                        int h, int w, float* I2, T* x0u, int ld) {
+__global__ void final_k(const ViewDesc* views, const CamDev* cams, const float* FM, int h, int w,
+                        float* I2, T* x0u, int ld) {
   const int v = blockIdx.y;
   const long P = (long)h * w;
   const long p = (long)blockIdx.x * TPB + threadIdx.x;
@@ -190,8 +190,8 @@ __global__ void final_k(const ViewDesc* views, const float* FM, const float* X4,
   const float* f = FM + ((long)v * P + p) * 8;
   const float4 F = ld4(f);
   const float M = f[4];
-  const float* Lc = X4 + d.cam_l * cam_stride;
-  const float* Rc = X4 + d.cam_r * cam_stride;
+  const float* Lc = cams[d.cam_l].X4;
+  const float* Rc = cams[d.cam_r].X4;
   const float4 L = ld4(Lc + 4 * p), R = ld4(Rc + 4 * p);
   const float4 Wl = sample4(Lc, warp_taps(xx, y, F.x, F.y, w, h));
   const float4 Wr = sample4(Rc, warp_taps(xx, y, F.z, F.w, w, h));
@@ -234,7 +234,7 @@ __global__ void flow_down_k(const float* in, int in_ld, int h, int w, float* out
 // One thread per (pixel, 8-channel group); groups [0, C/8) warp the left
 // camera's features by F_l, groups [C/8, C/4) the right's by F_r.
 template <typename T>
-__global__ void ctx_warp_k(const ViewDesc* views, const T* feat, long cam_stride, int C,
+__global__ void ctx_warp_k(const ViewDesc* views, const CamDev* cams, int level, int C,
                            const float* flow, int h, int w, T* dst, int dst_ld, long dst_img_stride) {
   const int v = blockIdx.y;
   const int G = C / 4;  // groups for both sides
@@ -249,7 +249,7 @@ __global__ void ctx_warp_k(const ViewDesc* views, const T* feat, long cam_stride
   const int y = (int)(p / w), x = (int)(p % w);
   const float4 F = ld4(flow + ((long)v * P + p) * 4);
   const Tap4 t = right ? warp_taps(x, y, F.z, F.w, w, h) : warp_taps(x, y, F.x, F.y, w, h);
-  const T* src = feat + (right ? d.cam_r : d.cam_l) * cam_stride + c0;
+  const T* src = reinterpret_cast<const T*>(cams[right ? d.cam_r : d.cam_l].ctx[level]) + c0;
   float acc[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) acc[i] = 0.f;
@@ -271,7 +271,7 @@ __global__ void ctx_warp_k(const ViewDesc* views, const T* feat, long cam_stride
 // written planar [3][H][W]. C (the U-Net's last width) is at most 64.
 template <typename T>
 __global__ void head_k(const T* u4, int ld, int C, const float* wgt, const float* bias,
-                       const float* I2, int Hp, int Wp, int H, int W, float* out) {
+                       const float* I2, const ViewDesc* views, int Hp, int Wp, int H, int W) {
   __shared__ float ws[3 * 64 * 9 + 3];
   const int nw = 3 * C * 9;
   for (int i = threadIdx.x; i < nw; i += TPB) ws[i] = wgt[i];
@@ -302,7 +302,7 @@ __global__ void head_k(const T* u4, int ld, int C, const float* wgt, const float
   const float4 b = ld4(I2 + ((long)v * Hp * Wp + (long)y * Wp + x) * 4);
   const float r0 = 1.f / (1.f + expf(-z0)), r1 = 1.f / (1.f + expf(-z1)), r2 = 1.f / (1.f + expf(-z2));
   const long HW = (long)H * W;
-  float* o = out + (long)v * 3 * HW;
+  float* o = views[v].out;
   o[p] = fminf(fmaxf(b.x + 2.f * r0 - 1.f, 0.f), 1.f);
   o[HW + p] = fminf(fmaxf(b.y + 2.f * r1 - 1.f, 0.f), 1.f);
   o[2 * HW + p] = fminf(fmaxf(b.z + 2.f * r2 - 1.f, 0.f), 1.f);
@@ -359,41 +359,40 @@ hipError_t launch_resample4(const float* in, int n_img, int Hi, int Wi, float* o
   return hipGetLastError();
 }
 
-hipError_t launch_assemble0(const ViewDesc* views, int n_views, const float* L0, long cam_stride,
-                            int h, int w, void* x, int ld, DType dt, int t_plane, hipStream_t s) {
+hipError_t launch_assemble0(const ViewDesc* views, int n_views, const CamDev* cams, int h, int w,
+                            void* x, int ld, DType dt, int t_plane, hipStream_t s) {
   if (n_views <= 0) return hipSuccess;
   if (dt == DType::F32)
-    hipLaunchKernelGGL(assemble0_k<float>, grid1((long)h * w, n_views), dim3(TPB), 0, s, views, L0,
-                       cam_stride, h, w, (float*)x, ld, t_plane);
+    hipLaunchKernelGGL(assemble0_k<float>, grid1((long)h * w, n_views), dim3(TPB), 0, s, views, cams,
+                       h, w, (float*)x, ld, t_plane);
   else
-    hipLaunchKernelGGL(assemble0_k<bf16>, grid1((long)h * w, n_views), dim3(TPB), 0, s, views, L0,
-                       cam_stride, h, w, (bf16*)x, ld, t_plane);
+    hipLaunchKernelGGL(assemble0_k<bf16>, grid1((long)h * w, n_views), dim3(TPB), 0, s, views, cams,
+                       h, w, (bf16*)x, ld, t_plane);
   return hipGetLastError();
 }
 
-hipError_t launch_transition(const ViewDesc* views, int n_views, const float* FMprev, int hp, int wp,
-                             const float* Limg, long cam_stride, int h, int w, void* x, int ld,
+hipError_t launch_transition(const ViewDesc* views, int n_views, const CamDev* cams, int level,
+                             const float* FMprev, int hp, int wp, int h, int w, void* x, int ld,
                              float* FM, DType dt, int t_plane, hipStream_t s) {
   if (n_views <= 0) return hipSuccess;
   if (dt == DType::F32)
-    hipLaunchKernelGGL(transition_k<float>, grid1((long)h * w, n_views), dim3(TPB), 0, s, views,
-                       FMprev, hp, wp, Limg, cam_stride, h, w, (float*)x, ld, FM, t_plane);
+    hipLaunchKernelGGL(transition_k<float>, grid1((long)h * w, n_views), dim3(TPB), 0, s, views, cams,
+                       level, FMprev, hp, wp, h, w, (float*)x, ld, FM, t_plane);
   else
-    hipLaunchKernelGGL(transition_k<bf16>, grid1((long)h * w, n_views), dim3(TPB), 0, s, views,
-                       FMprev, hp, wp, Limg, cam_stride, h, w, (bf16*)x, ld, FM, t_plane);
+    hipLaunchKernelGGL(transition_k<bf16>, grid1((long)h * w, n_views), dim3(TPB), 0, s, views, cams,
+                       level, FMprev, hp, wp, h, w, (bf16*)x, ld, FM, t_plane);
   return hipGetLastError();
 }
 
-hipError_t launch_final(const ViewDesc* views, int n_views, const float* FM, const float* X4,
-                        long cam_stride, int h, int w, float* I2, void* x0u, int ld, DType dt,
-                        hipStream_t s) {
+hipError_t launch_final(const ViewDesc* views, int n_views, const CamDev* cams, const float* FM,
+                        int h, int w, float* I2, void* x0u, int ld, DType dt, hipStream_t s) {
   if (n_views <= 0) return hipSuccess;
   if (dt == DType::F32)
-    hipLaunchKernelGGL(final_k<float>, grid1((long)h * w, n_views), dim3(TPB), 0, s, views, FM, X4,
-                       cam_stride, h, w, I2, (float*)x0u, ld);
+    hipLaunchKernelGGL(final_k<float>, grid1((long)h * w, n_views), dim3(TPB), 0, s, views, cams, FM, h,
+                       w, I2, (float*)x0u, ld);
   else
-    hipLaunchKernelGGL(final_k<bf16>, grid1((long)h * w, n_views), dim3(TPB), 0, s, views, FM, X4,
-                       cam_stride, h, w, I2, (bf16*)x0u, ld);
+    hipLaunchKernelGGL(final_k<bf16>, grid1((long)h * w, n_views), dim3(TPB), 0, s, views, cams, FM, h,
+                       w, I2, (bf16*)x0u, ld);
   return hipGetLastError();
 }
 
@@ -405,34 +404,32 @@ hipError_t launch_flow_down(const float* in, int in_ld, int n_img, int h, int w,
   return hipGetLastError();
 }
 
-hipError_t launch_ctx_warp(const ViewDesc* views, int n_views, const void* feat, long cam_stride,
-                           int C, const float* flow, int h, int w, void* dst, int dst_ld,
+hipError_t launch_ctx_warp(const ViewDesc* views, int n_views, const CamDev* cams, int level, int C,
+                           const float* flow, int h, int w, void* dst, int dst_ld,
                            long dst_img_stride, DType dt, hipStream_t s) {
   if (n_views <= 0) return hipSuccess;
   if (C % 8 != 0) return hipErrorInvalidValue;
   const long n = (long)h * w * (C / 4);
   if (dt == DType::F32)
-    hipLaunchKernelGGL(ctx_warp_k<float>, grid1(n, n_views), dim3(TPB), 0, s, views,
-                       (const float*)feat, cam_stride, C, flow, h, w, (float*)dst, dst_ld,
-                       dst_img_stride);
+    hipLaunchKernelGGL(ctx_warp_k<float>, grid1(n, n_views), dim3(TPB), 0, s, views, cams, level, C,
+                       flow, h, w, (float*)dst, dst_ld, dst_img_stride);
   else
-    hipLaunchKernelGGL(ctx_warp_k<bf16>, grid1(n, n_views), dim3(TPB), 0, s, views,
-                       (const bf16*)feat, cam_stride, C, flow, h, w, (bf16*)dst, dst_ld,
-                       dst_img_stride);
+    hipLaunchKernelGGL(ctx_warp_k<bf16>, grid1(n, n_views), dim3(TPB), 0, s, views, cams, level, C,
+                       flow, h, w, (bf16*)dst, dst_ld, dst_img_stride);
   return hipGetLastError();
 }
 
 hipError_t launch_head(const void* u4, int ld, int C, const float* w, const float* b,
-                       const float* I2, int n_img, int Hp, int Wp, int H, int W, float* out,
-                       DType dt, hipStream_t s) {
+                       const float* I2, const ViewDesc* views, int n_img, int Hp, int Wp, int H,
+                       int W, DType dt, hipStream_t s) {
   if (n_img <= 0) return hipSuccess;
   if (C > 64 || C > ld) return hipErrorInvalidValue;
   if (dt == DType::F32)
     hipLaunchKernelGGL(head_k<float>, grid1((long)H * W, n_img), dim3(TPB), 0, s,
-                       (const float*)u4, ld, C, w, b, I2, Hp, Wp, H, W, out);
+                       (const float*)u4, ld, C, w, b, I2, views, Hp, Wp, H, W);
   else
     hipLaunchKernelGGL(head_k<bf16>, grid1((long)H * W, n_img), dim3(TPB), 0, s,
-                       (const bf16*)u4, ld, C, w, b, I2, Hp, Wp, H, W, out);
+                       (const bf16*)u4, ld, C, w, b, I2, views, Hp, Wp, H, W);
   return hipGetLastError();
 }
 

@@ -25,8 +25,8 @@ STATUS = {0: "FFV_OK", 1: "FFV_PENDING", -1: "FFV_ERR_ARG", -2: "FFV_ERR_OOM",
 
 # Every symbol include/ffv.h declares.
 EXPORTS = ["ffv_default_opts", "ffv_create_net", "ffv_destroy_net", "ffv_interpolate",
-           "ffv_last_error", "ffv_debug_tap", "ffv_set_debug", "ffv_set_profiling",
-           "ffv_kernel_stats", "ffv_op_conv"]
+           "ffv_last_error", "ffv_register_camera", "ffv_submit", "ffv_poll", "ffv_serving_stats",
+           "ffv_debug_tap", "ffv_set_debug", "ffv_set_profiling", "ffv_kernel_stats", "ffv_op_conv"]
 
 
 class FfvError(RuntimeError):
@@ -41,6 +41,16 @@ class ffv_opts(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
                 ("hbm_budget_bytes", ctypes.c_uint64), ("tick_ms", ctypes.c_float),
                 ("max_batch_views", ctypes.c_int32)]
+
+
+class ffv_request(ctypes.Structure):
+    _fields_ = [("cam_left", ctypes.c_int32), ("cam_right", ctypes.c_int32),
+                ("t", ctypes.c_float), ("out", ctypes.c_void_p), ("user_tag", ctypes.c_uint64)]
+
+
+class ffv_timing(ctypes.Structure):
+    _fields_ = [("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double)]
 
 
 class ffv_pair(ctypes.Structure):
@@ -83,6 +93,16 @@ def lib() -> ctypes.CDLL:
     L.ffv_op_conv.argtypes = [c_int, c_void, c_int, c_int, c_int, c_int, c_void, c_void, c_int,
                               c_int, c_int, c_int, c_void, c_void]
     L.ffv_op_conv.restype = c_int
+    L.ffv_register_camera.argtypes = [c_void, c_int, c_void, c_int, c_int]
+    L.ffv_register_camera.restype = c_int
+    L.ffv_submit.argtypes = [c_void, ctypes.POINTER(ffv_request), ctypes.POINTER(ctypes.c_uint64)]
+    L.ffv_submit.restype = c_int
+    L.ffv_poll.argtypes = [c_void, ctypes.c_uint64, ctypes.POINTER(ffv_timing)]
+    L.ffv_poll.restype = c_int
+    L.ffv_serving_stats.argtypes = [c_void, ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(ctypes.c_uint64)]
+    L.ffv_serving_stats.restype = c_int
     _lib = L
     return L
 
@@ -106,7 +126,8 @@ class Net:
     """A loaded network on one GPU. ``precision`` is "fp32" or "bf16"."""
 
     def __init__(self, weights_path: str, precision: str = "fp32", device: int = 0,
-                 workspace_bytes: int = 0):
+                 workspace_bytes: int = 0, hbm_budget_bytes: int = 0, tick_ms: float = 5.0,
+                 max_batch_views: int = 0):
         L = lib()
         self.device = torch.device("cuda", device)
         # The library works on this stream; calls order it after the caller's
@@ -118,6 +139,9 @@ class Net:
         opts.device = device
         opts.stream = self.stream.cuda_stream
         opts.workspace_bytes = workspace_bytes
+        opts.hbm_budget_bytes = hbm_budget_bytes
+        opts.tick_ms = tick_ms
+        opts.max_batch_views = max_batch_views
         h = ctypes.c_void_p()
         _check(L.ffv_create_net(os.fsencode(weights_path), ctypes.byref(opts), ctypes.byref(h)))
         self._h = h
@@ -159,6 +183,44 @@ class Net:
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
         _check(lib().ffv_interpolate(self._h, arr, len(pairs), tarr, len(ts), out.data_ptr()))
         return out
+
+    # ---------------------------------------------------------------- serving
+    def register_camera(self, cam_id: int, image: torch.Tensor):
+        """Make ``image`` ([3, H, W] float32 CUDA) resident as camera ``cam_id``."""
+        _dev_f32(image, "image")
+        if image.dim() != 3 or image.shape[0] != 3:
+            raise ValueError("image must be [3, H, W]")
+        torch.cuda.current_stream(self.device).synchronize()
+        _check(lib().ffv_register_camera(self._h, cam_id, image.data_ptr(), int(image.shape[1]),
+                                         int(image.shape[2])))
+
+    def submit(self, cam_left: int, cam_right: int, t: float, out: torch.Tensor,
+               tag: int = 0) -> int:
+        """Queue one view; ``out`` ([3, H, W] float32 CUDA) must stay alive
+        until ``poll`` reports it done. Returns the ticket."""
+        _dev_f32(out, "out")
+        req = ffv_request(cam_left, cam_right, float(t), out.data_ptr(), tag)
+        tk = ctypes.c_uint64()
+        torch.cuda.current_stream(self.device).synchronize()
+        _check(lib().ffv_submit(self._h, ctypes.byref(req), ctypes.byref(tk)))
+        return tk.value
+
+    def poll(self, ticket: int):
+        """None while pending; the timing dict once the view is written."""
+        tm = ffv_timing()
+        code = _check(lib().ffv_poll(self._h, ticket, ctypes.byref(tm)))
+        if code == 1:
+            return None
+        return {"t_submit": tm.t_submit, "t_admit": tm.t_admit, "t_launch": tm.t_launch,
+                "t_done": tm.t_done}
+
+    def serving_stats(self):
+        a, c, q = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        b = ctypes.c_uint64()
+        _check(lib().ffv_serving_stats(self._h, ctypes.byref(a), ctypes.byref(c), ctypes.byref(q),
+                                       ctypes.byref(b)))
+        return {"admitted": a.value, "completed": c.value, "queued": q.value,
+                "bytes_in_use": b.value}
 
     def set_debug(self, on: bool = True):
         _check(lib().ffv_set_debug(self._h, 1 if on else 0))
