@@ -44,6 +44,82 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
+def serve_leg(wpath, dev, seconds, rate_fraction=None, capacity=None, users=64, per_user_rps=30.0,
+              max_batch=32, budget=64 << 30, tick_ms=5.0, pool=256):
+    """Multi-user serving: two 8-camera arcs (1280x720 and 1920x1080), each
+    request a random adjacent pair, t ~ U(0, 1), resolution 50/50; Poisson
+    arrivals (users x per_user_rps, or rate_fraction x capacity). Requests
+    that find no free output buffer are shed. Returns counts and latency
+    percentiles of completed requests (submit -> written)."""
+    import numpy as np
+    import torch
+
+    from paper_2112_10603_amd import Net
+    from synth import scenes
+
+    net = Net(wpath, "bf16", 0, hbm_budget_bytes=budget, tick_ms=tick_ms, max_batch_views=max_batch)
+    arcs = {720: scenes.camera_arc(50, 720, 1280, 8, 1024, (8.0, 64.0), 48.0, 0.01, device=dev),
+            1080: scenes.camera_arc(51, 1080, 1920, 8, 1024, (8.0, 64.0), 48.0, 0.01, device=dev)}
+    for res, arc in arcs.items():
+        for j in range(8):
+            net.register_camera(res * 100 + j, arc[j].contiguous())
+    bufs = {res: [torch.empty((3,) + tuple(arcs[res].shape[2:]), device=dev) for _ in range(pool)]
+            for res in arcs}
+    free = {res: list(range(pool)) for res in arcs}
+    rate = users * per_user_rps if rate_fraction is None else rate_fraction * capacity
+    rng = np.random.default_rng(52)
+    n_max = int(rate * seconds * 1.5) + 10
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_max))
+    arrivals = arrivals[arrivals < seconds]
+    res_pick = rng.random(len(arrivals)) < 0.5
+    pair_pick = rng.integers(0, 7, len(arrivals))
+    t_pick = rng.uniform(0.0, 1.0, len(arrivals))
+    pending = {}
+    lat = []
+    shed = 0
+    i = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while True:
+        now = time.perf_counter() - t0
+        while i < len(arrivals) and arrivals[i] <= now:
+            res = 720 if res_pick[i] else 1080
+            if free[res]:
+                b = free[res].pop()
+                cam = res * 100 + int(pair_pick[i])
+                tk = net.submit(cam, cam + 1, float(t_pick[i]), bufs[res][b])
+                pending[tk] = (res, b)
+            else:
+                shed += 1
+            i += 1
+        for tk in list(pending):
+            tm = net.poll(tk)
+            if tm is not None:
+                res, b = pending.pop(tk)
+                free[res].append(b)
+                if now <= seconds:
+                    lat.append(1000.0 * (tm["t_done"] - tm["t_submit"]))
+        if now > seconds:
+            break
+        time.sleep(0.0005)
+    window = time.perf_counter() - t0
+    st = net.serving_stats()
+    in_flight = len(pending)
+    # drain what was admitted before closing (outputs must stay alive)
+    while pending:
+        for tk in list(pending):
+            if net.poll(tk) is not None:
+                pending.pop(tk)
+        time.sleep(0.001)
+    net.close()
+    return {"offered_rps": round(len(arrivals) / seconds, 1),
+            "completed_views_per_s": round(len(lat) / window, 2),
+            "p50_ms": round(percentile(lat, 0.5), 2), "p99_ms": round(percentile(lat, 0.99), 2),
+            "completed": len(lat), "shed_no_buffer": shed, "in_flight_at_end": in_flight,
+            "admitted": st["admitted"], "window_s": round(window, 2), "max_batch_views": max_batch,
+            "budget_gib": budget >> 30, "tick_ms": tick_ms}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,6 +131,10 @@ def main():
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--phases", type=int, default=16)
     ap.add_argument("--cams", type=int, default=8)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="first run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): each view is independent, "
@@ -70,6 +150,13 @@ def main():
     from synth.weights import write_weights_file
 
     dev = torch.device("cuda:0")
+    if args.copy_calib:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] copy calibration: 1 GiB read + 1 GiB written", file=sys.stderr, flush=True)
+        del src, dst
     H, W = args.height, args.width
     td = tempfile.mkdtemp()
     wpath = write_weights_file(os.path.join(td, "w.ffvw"), seed=0)
@@ -149,6 +236,21 @@ def main():
         net32.close()
         print(f"[bench] fp32 plain {v32:.2f} views/s", file=sys.stderr, flush=True)
 
+    serving = None
+    if not args.no_serve:
+        sat = serve_leg(wpath, dev, args.serve_seconds)
+        print(f"[bench] serving at offered {sat['offered_rps']} req/s: "
+              f"{sat['completed_views_per_s']} views/s, p99 {sat['p99_ms']} ms",
+              file=sys.stderr, flush=True)
+        sub = serve_leg(wpath, dev, args.serve_seconds, rate_fraction=0.7,
+                        capacity=max(1.0, sat["completed_views_per_s"]))
+        print(f"[bench] serving at 70% capacity: p50 {sub['p50_ms']} ms, p99 {sub['p99_ms']} ms",
+              file=sys.stderr, flush=True)
+        serving = {"workload": "two 8-camera arcs (1280x720, 1920x1080), 64 users x 30 req/s "
+                               "Poisson, random adjacent pair, t~U(0,1), 50/50 resolution, "
+                               "5 ms tick, 64 GiB budget, BF16",
+                   "saturation": sat, "at_70pct_capacity": sub}
+
     cpu = None
     psnr = None
     if not args.no_oracle:
@@ -192,8 +294,10 @@ def main():
         "cpu_baseline": cpu,
         "psnr_db_vs_oracle": None if psnr is None else round(psnr, 2),
         "latency_ms": {"p50": round(percentile(step_ms, 0.5), 3),
-                       "p99": round(percentile(step_ms, 0.99), 3), "per": "step"},
+                       "p99": round(percentile(step_ms, 0.99), 3),
+                       "per": "step of the dense-view batch (serving request latency in 'serving')"},
         "fp32_plain": fp32,
+        "serving": serving,
         "bf16_vs_fp32": None if fp32 is None else round(value / fp32["views_per_s"], 2),
         "conv_mfma_util": round(conv_flops / (conv_ms * 1e-3) / 1e12 / PEAK_BF16_TFLOPS, 4)
         if conv_ms > 0 else None,
