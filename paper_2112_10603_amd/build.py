@@ -56,6 +56,15 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    # C-ABI-only driver (no Python): links the library through its rpath
+    drv_src = os.path.join(PKG, "driver", "ffv_drive.hip")
+    drv = os.path.join(LIBDIR, "ffv_drive")
+    cmd = [_hipcc(), "-xhip", *COMMON, *DEVICE, drv_src, "-o", drv + ".tmp", f"-L{LIBDIR}", "-lffv",
+           "-Wl,-rpath,$ORIGIN"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"driver build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(drv + ".tmp", drv)
     if verbose:
         print(f"built {LIB}")
     return LIB

@@ -270,6 +270,7 @@ extern "C" ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, 
     a.accumulate = 0;
     a.taps = L.mode == 1 ? 4 : 9;
     a.zero = zr;
+    a.tile_w = conv_tile_width(a.Ho, a.Wo);
     err = launch_conv(dt, L.tile, a, s);
   }
   for (int i = 0; err == hipSuccess && i < n; ++i)

@@ -49,6 +49,7 @@ struct ConvArgs {
   int out_f32;          // 1: float output, 0: activation dtype
   int accumulate;       // 1: add into the existing float output
   int taps;             // taps in K (9, or 4 for one transposed phase)
+  int tile_w;           // width of the 2-D pixel block of an M tile (divides the M tile)
   const void* zero;     // >= 16 bytes of zeros (read for taps outside the image)
 };
 
@@ -56,6 +57,9 @@ struct ConvArgs {
 enum class ConvTile : int { N256 = 0, N128 = 1, N64 = 2, N32 = 3 };
 
 hipError_t launch_conv(DType dt, ConvTile tile, const ConvArgs& a, hipStream_t s);
+// Width of the 2-D pixel block of a 256-pixel M tile for a Ho x Wo grid:
+// the least padded area, the squarest block on ties.
+int conv_tile_width(int Ho, int Wo);
 // K elements per pipeline step of the conv kernel for a dtype.
 int conv_k_step(DType dt);
 

@@ -1,5 +1,6 @@
 // Instantiations of the implicit-GEMM convolution kernel (conv_kernel.h)
-// used by the library, one per N-tile class.
+// used by the library, one per N-tile class. All use 128-byte K steps
+// (conv_k_step), which the weight packing's K order depends on.
 #include "conv_kernel.h"
 
 namespace ffv {
@@ -25,6 +26,20 @@ hipError_t launch_t(ConvTile tile, const ConvArgs& a, hipStream_t s) {
 }  // namespace
 
 int conv_k_step(DType dt) { return dt == DType::F32 ? 32 : 64; }
+
+int conv_tile_width(int Ho, int Wo) {
+  int best = 16;
+  long best_area = -1;
+  for (int tw : {16, 32, 8, 64, 128, 256}) {
+    const int th = 256 / tw;
+    const long area = (long)((Ho + th - 1) / th) * th * ((Wo + tw - 1) / tw) * tw;
+    if (best_area < 0 || area < best_area) {
+      best_area = area;
+      best = tw;
+    }
+  }
+  return best;
+}
 
 hipError_t launch_conv(DType dt, ConvTile tile, const ConvArgs& a, hipStream_t s) {
   if (a.n_img <= 0 || a.Ho <= 0 || a.Wo <= 0) return hipSuccess;

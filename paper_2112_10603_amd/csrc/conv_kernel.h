@@ -9,8 +9,10 @@
 // once for all four phases.
 //
 // GEMM view: M = output pixels (images folded in), N = output channels,
-// K = (tap, input channel). A workgroup of WM x WN waves computes a BM x BN
-// tile; each wave owns a block of 32x32 MFMA fragments. Each K step covers
+// K = (tap, input channel). The BM pixels of an M tile form a 2-D block of
+// the grid (BM / tile_w rows of tile_w pixels), so the input rows its 3x3
+// taps read are shared by the block's own rows and stay in cache. A
+// workgroup of WM x WN waves computes a BM x BN tile; each wave owns a block of 32x32 MFMA fragments. Each K step covers
 // KB bytes of every A and B row: the A tile is gathered from NHWC
 // activations, the B tile read from packed weights (K contiguous). Both go
 // straight from global memory into LDS with global_load_lds_dwordx4 (no
@@ -151,9 +153,12 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   const int xcd = bx & 7, q = gx >> 3, r = gx & 7;
   const int mt = xcd * q + min(xcd, r) + (bx >> 3);
 
-  const long HW = (long)a.Ho * a.Wo;
-  const long M = (long)a.n_img * HW;
-  const long m0 = (long)mt * BM;
+  // 2-D M tile: image, tile row, tile column
+  const int TW = a.tile_w, TH = BM / a.tile_w;
+  const int tiles_x = (a.Wo + TW - 1) / TW, tiles_y = (a.Ho + TH - 1) / TH;
+  const int img_t = mt / (tiles_x * tiles_y);
+  const int rem_t = mt - img_t * tiles_x * tiles_y;
+  const int ty0 = (rem_t / tiles_x) * TH, tx0 = (rem_t % tiles_x) * TW;
   const int n0 = blockIdx.y * BN;
   const int chunk = tid % CH;  // this thread's chunk within a row
 
@@ -170,14 +175,9 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   for (int i = 0; i < A_IT; ++i) {
     const int v = tid + i * NT;
     const int row = v / CH;
-    const long m = m0 + row;
-    a_ok[i] = (v < A_VECS) && (m < M);
-    const long mm = a_ok[i] ? m : 0;
-    const long img = mm / HW;
-    const int rem = (int)(mm - img * HW);
-    const int oy = rem / a.Wo;
-    const int ox = rem - oy * a.Wo;
-    a_base[i] = in + img * a.in_img_stride;
+    const int oy = ty0 + row / TW, ox = tx0 + row % TW;
+    a_ok[i] = (v < A_VECS) && (oy < a.Ho) && (ox < a.Wo);
+    a_base[i] = in + (long)img_t * a.in_img_stride;
     a_iy[i] = oy * a.stride;
     a_ix[i] = ox * a.stride;
     a_ch[i] = C::logical_chunk(row, chunk);
@@ -199,11 +199,15 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   const bool tap_uniform = (a.cin_pad % BK) == 0;
 
   auto issue = [&](int kc, int buf) {
+    // K order: when a step stays inside one tap (channels a multiple of BK)
+    // the steps run channel-slice major, all taps of a slice back to back,
+    // so the input lines a slice needs are reused while still in L2;
+    // otherwise tap major. The packed weights use the same order.
     int tap_u = 0, c_u = 0;
     if (tap_uniform) {
-      const int k0 = kc * BK;
-      tap_u = k0 / a.cin_pad;
-      c_u = k0 - tap_u * a.cin_pad;
+      const int slice = kc / a.taps;
+      tap_u = kc - slice * a.taps;
+      c_u = slice * BK;
     }
 #pragma unroll
     for (int i = 0; i < A_IT; ++i) {
@@ -226,7 +230,9 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
         dx = tap - (tap / 3) * 3 - 1;
       }
       const int iy = a_iy[i] + dy, ix = a_ix[i] + dx;
-      const bool ok = a_ok[i] && tap < a.taps && iy >= 0 && iy < a.Hi && ix >= 0 && ix < a.Wi;
+      // steps past the real K (K padded to the step) read nothing
+      const bool kin = tap_uniform ? c_u < a.cin_pad : tap < a.taps;
+      const bool ok = a_ok[i] && kin && iy >= 0 && iy < a.Hi && ix >= 0 && ix < a.Wi;
       const T* src = ok ? a_base[i] + ((long)iy * a.Wi + ix) * a.in_ld + c : zero;
       if (A_VECS % NT == 0 || tid + i * NT < A_VECS)
         load_to_lds(src, &As[buf][i * NT + wave * 64]);
@@ -291,18 +297,14 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int row = wm * TM + i * 32 + (e >> 2) * 8 + lhalf * 4 + (e & 3);
-      const long m = m0 + row;
-      row_ok[e] = m < M;
-      const long mm = row_ok[e] ? m : 0;
-      const long img = mm / HW;
-      const int rem = (int)(mm - img * HW);
-      int oy = rem / a.Wo;
-      int ox = rem - oy * a.Wo;
+      int oy = ty0 + row / TW;
+      int ox = tx0 + row % TW;
+      row_ok[e] = oy < a.Ho && ox < a.Wo;
       if (a.transposed) {  // output of the GEMM grid point (oy, ox), phase (0, 0)
         oy *= 2;
         ox *= 2;
       }
-      off_row[e] = img * a.out_img_stride + ((long)(oy + py) * a.Wout + ox + px) * a.out_ld;
+      off_row[e] = (long)img_t * a.out_img_stride + ((long)(oy + py) * a.Wout + ox + px) * a.out_ld;
     }
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
@@ -334,12 +336,12 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
 template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES, int SWZ = 0>
 hipError_t launch_variant(const ConvArgs& a, hipStream_t s) {
   using C = Conv<T, BM, BN, WM, WN, KB, STAGES, SWZ>;
-  const long M = (long)a.n_img * a.Ho * a.Wo;
   const int phases = a.transposed == 1 ? 4 : 1;
   if (a.K_pad % C::BK != 0 || a.cin_pad % C::VEC != 0 || a.cout_pad % BN != 0 ||
-      a.in_ld % C::VEC != 0)
+      a.in_ld % C::VEC != 0 || a.tile_w <= 0 || BM % a.tile_w != 0)
     return hipErrorInvalidValue;
-  const long tiles = (M + BM - 1) / BM;
+  const long tiles = (long)a.n_img * ((a.Ho + BM / a.tile_w - 1) / (BM / a.tile_w)) *
+                     ((a.Wo + a.tile_w - 1) / a.tile_w);
   if (tiles > 0x7fffffffL) return hipErrorInvalidValue;
   dim3 grid((unsigned)tiles, (unsigned)(a.cout_pad / BN), phases);
   hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES, SWZ>), grid, dim3(C::NT), 0, s, a);

@@ -184,20 +184,27 @@ void plan_layer(Layer& L) {
 
 std::vector<uint8_t> pack_layer(const Layer& L, DType dt) {
   const int phases = L.mode == 1 ? 4 : 1;
+  const int taps = L.mode == 1 ? 4 : 9;
   const size_t n = (size_t)phases * L.cout_pad * L.K_pad;
+  // K position of (tap, channel): channel-slice major when the channel count
+  // is a multiple of the kernel's K step (as the kernel walks K), else tap major.
+  const int bk = conv_k_step(dt);
+  const bool slice_major = L.cin_pad % bk == 0;
+  auto kpos = [&](int tap, int c) {
+    if (!slice_major) return tap * L.cin_pad + c;
+    return ((c / bk) * taps + tap) * bk + (c % bk);
+  };
   std::vector<float> p(n, 0.f);
   if (L.mode == 0) {
-    // k = (dy*3 + dx) * cin_pad + c  <-  w[o][c][dy][dx]
+    // tap = dy*3 + dx  <-  w[o][c][dy][dx]
     for (int o = 0; o < L.cout; ++o) {
       float* row = &p[(size_t)o * L.K_pad];
       for (int c = 0; c < L.cin; ++c)
-        for (int tap = 0; tap < 9; ++tap)
-          row[tap * L.cin_pad + c] = L.w_host[((size_t)o * L.cin + c) * 9 + tap];
+        for (int tap = 0; tap < 9; ++tap) row[kpos(tap, c)] = L.w_host[((size_t)o * L.cin + c) * 9 + tap];
     }
   } else if (L.mode == 1) {
     // phase (py, px), tap (ty, tx) reads input (a + py - ty, b + px - tx) with
-    // kernel index (1 - py + 2ty, 1 - px + 2tx);
-    // k = (ty*2 + tx) * cin_pad + c  <-  w[c][o][ky][kx]
+    // kernel index (1 - py + 2ty, 1 - px + 2tx); tap = ty*2 + tx  <-  w[c][o][ky][kx]
     for (int ph = 0; ph < 4; ++ph) {
       const int py = ph >> 1, px = ph & 1;
       for (int o = 0; o < L.cout; ++o) {
@@ -206,14 +213,13 @@ std::vector<uint8_t> pack_layer(const Layer& L, DType dt) {
           for (int ty = 0; ty < 2; ++ty)
             for (int tx = 0; tx < 2; ++tx) {
               const int ky = 1 - py + 2 * ty, kx = 1 - px + 2 * tx;
-              row[(ty * 2 + tx) * L.cin_pad + c] =
-                  L.w_host[(((size_t)c * L.cout + o) * 4 + ky) * 4 + kx];
+              row[kpos(ty * 2 + tx, c)] = L.w_host[(((size_t)c * L.cout + o) * 4 + ky) * 4 + kx];
             }
       }
     }
   } else {
-    // phase-merged: row n = ph * cout + o, k = ((dy+1)*3 + (dx+1)) * cin_pad + c
-    // over the input's 3x3 neighbourhood; phase (py, px) uses the taps with
+    // phase-merged: row n = ph * cout + o, tap = (dy+1)*3 + (dx+1) over the
+    // input's 3x3 neighbourhood; phase (py, px) uses the taps with
     // ty = py - dy and tx = px - dx in {0, 1}, kernel index (1 - py + 2ty, 1 - px + 2tx).
     for (int ph = 0; ph < 4; ++ph) {
       const int py = ph >> 1, px = ph & 1;
@@ -226,7 +232,7 @@ std::vector<uint8_t> pack_layer(const Layer& L, DType dt) {
             const int ky = 1 - py + 2 * ty, kx = 1 - px + 2 * tx;
             const int tap = (dy + 1) * 3 + (dx + 1);
             for (int c = 0; c < L.cin; ++c)
-              row[tap * L.cin_pad + c] = L.w_host[(((size_t)c * L.cout + o) * 4 + ky) * 4 + kx];
+              row[kpos(tap, c)] = L.w_host[(((size_t)c * L.cout + o) * 4 + ky) * 4 + kx];
           }
       }
     }
@@ -501,6 +507,7 @@ Status Net::conv(const Exec& x, const Layer& L, const void* in, int in_ld, long 
   a.accumulate = accumulate ? 1 : 0;
   a.taps = L.mode == 1 ? 4 : 9;
   a.zero = zero_;
+  a.tile_w = conv_tile_width(a.Ho, a.Wo);
   if (in_ld < L.cin_pad || in_ld % 8 != 0) return Status::err(-4, "conv input stride");
   const double flops = 2.0 * n_img * (double)a.Hout * a.Wout * L.cout * L.cin *
                        (L.transposed ? 4.0 : 9.0);

@@ -10,7 +10,9 @@ analytic colour texture seen through a smooth horizontal disparity field:
   condition on the sample coordinate, so shifted copies stay exact);
 * disparity ``D(x, y)``: a sum of 16 Gaussians, rescaled to span exactly
   ``[0, d_max]`` over the pixel grid;
-* camera ``j``: ``C_j(x, y) = clip(T(x + j*D(x, y), y) + N(0, noise^2), 0, 1)``.
+* camera ``j``: ``C_j(x, y) = clip(T(x + j*D(x, y), y) + N(0, noise^2), 0, 1)``,
+  the noise drawn by a torch generator on the target device, seeded from
+  the scene seed (so it is made where it is used, with no host copy).
 
 The small case uses a constant shift instead: the right view is the left
 view moved by exactly 4 px (``X_r(x, y) = T(x + 4, y)``), no noise.
@@ -125,11 +127,13 @@ def camera_arc(seed: int, H: int, W: int, n_cams: int, n_blobs: int,
     ys = torch.arange(H, dtype=torch.float64, device=device)[:, None].expand(H, W)
     xs = torch.arange(W, dtype=torch.float64, device=device)[None, :].expand(H, W)
     out = torch.empty((n_cams, 3, H, W), dtype=torch.float32, device=device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(rng.integers(0, 2**62)))
     for j in range(n_cams):
         T = _render_texture(p, xs + j * D, ys, (0.0, j * d_max), device)
         if noise > 0:
-            n = rng.standard_normal((3, H, W)) * noise
-            T = T + torch.from_numpy(n).to(device)
+            T = T + noise * torch.randn((3, H, W), generator=gen, dtype=torch.float64,
+                                        device=device)
         out[j] = T.clamp(0.0, 1.0).float()
     return out
 
