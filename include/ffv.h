@@ -45,14 +45,17 @@ typedef enum {
 typedef enum {
   FFV_FP32 = 0,      /* convolutions on fp32 MFMA, fp32 activations */
   FFV_BF16 = 1,      /* convolutions on bf16 MFMA with fp32 accumulation */
-  FFV_FP8_E4M3 = 2   /* reserved: fp8 e4m3 convolutions (not built) */
+  FFV_FP8_E4M3 = 2   /* VIBlock 128/256-channel convs in fp8 e4m3 (per-channel activation
+                        scales folded into per-output-channel weight scales, fp32
+                        accumulation); other convs bf16. Needs ffv_calibrate. */
 } ffv_precision;
 
 typedef struct {
   int32_t abi_version;          /* must be FFV_ABI_VERSION */
   int32_t precision;            /* ffv_precision */
   int32_t device;               /* HIP device ordinal */
-  int32_t reserved0;
+  int32_t graphs;               /* 1 (default): ffv_interpolate replays its launches as one
+                                   hipGraph per call shape, captured on first use; 0: eager */
   void* stream;                 /* hipStream_t to order against; NULL = library stream */
   uint64_t workspace_bytes;     /* cap on the per-call workspace; 0 = 16 GiB */
   uint64_t hbm_budget_bytes;    /* serving admission budget; 0 = serving off */
@@ -60,8 +63,8 @@ typedef struct {
   int32_t max_batch_views;      /* views per launch in serving; 0 = 64 */
 } ffv_opts;
 
-/* Fills *opts with the defaults (FP32, device 0, library stream, 16 GiB
- * workspace cap, serving off). */
+/* Fills *opts with the defaults (FP32, device 0, library stream, graphs on,
+ * 16 GiB workspace cap, serving off). */
 void ffv_default_opts(ffv_opts* opts);
 
 /*
@@ -93,15 +96,60 @@ typedef struct {
  *   t:   HOST array of n_t phases, each in [0, 1].
  *   out: DEVICE float32 [n_pairs][n_t][3][H][W], caller-owned.
  * Work is ordered on opts->stream (or the library stream); the call returns
- * after the output is written. Not thread-safe per net.
+ * after the output is written. Calls on one net are serialised. With
+ * opts->graphs the first call of a shape (H, W, number of distinct images,
+ * number of views) captures the whole launch sequence into a hipGraph and
+ * every later call of that shape replays it after writing the per-call
+ * tables (image pointers, t, output pointers) to device memory; the results
+ * are the same as eager launches (same kernels, same order).
  * Errors: FFV_ERR_ARG (nulls, n <= 0, mixed sizes, t outside [0,1] or NaN),
  * FFV_ERR_OOM, FFV_ERR_DEVICE.
  */
 ffv_status ffv_interpolate(ffv_net* net, const ffv_pair* views, int32_t n_pairs,
                            const float* t, int32_t n_t, float* out);
 
+/*
+ * Conv tile autotuning (the conv kernel is instantiated for 256-pixel M tiles
+ * with 256/128/64/32-channel N tiles; the 256 pixels form a tile_w-wide 2-D
+ * block). Runs the call exactly as ffv_interpolate does (same arguments, same
+ * result in *out*), then re-launches each convolution of that call with
+ * every candidate (N tile at most twice the real channel count rounded to
+ * 32; pixel-block widths 8, 16, 32, 64 within 10 % of the least padding),
+ * timed with HIP events on the net's stream, and keeps the fastest per
+ * (layer, fp8 or not, output grid, images per launch). Later calls whose
+ * launches match use those choices; captured graphs are dropped.
+ * *n_tuned (nullable) = launch shapes tuned. Takes seconds at 1080p batch
+ * sizes. Errors as ffv_interpolate.
+ */
+ffv_status ffv_autotune(ffv_net* net, const ffv_pair* views, int32_t n_pairs, const float* t,
+                        int32_t n_t, float* out, int32_t* n_tuned);
+
+/*
+ * Tuning table as text, one line per launch shape:
+ * "layer fp8 Ho Wo n_img n_tile tile_w" ('#' starts a comment line).
+ * ffv_save_tuning writes the net's table; ffv_load_tuning merges a file's
+ * entries into it (*n_loaded, nullable, = entries read) and rejects the
+ * whole file on a malformed line, an unknown layer or a tile that does not
+ * fit its layer (FFV_ERR_ARG).
+ */
+ffv_status ffv_save_tuning(ffv_net* net, const char* path);
+ffv_status ffv_load_tuning(ffv_net* net, const char* path, int32_t* n_loaded);
+
 /* Last error message of the calling thread (valid until its next call). */
 const char* ffv_last_error(void);
+
+/*
+ * FP8 nets only: run the view at phase t of `pair` once in bf16, record the
+ * range of every VIBlock activation channel (|value| max), and quantise the
+ * VIBlock layers that read those activations to fp8 e4m3: the producer's
+ * per-channel scale (max / 448) is folded into the weights, each output
+ * channel then gets its own weight scale, and activations are stored as
+ * value / scale, saturated to +-448. Must be called (with representative
+ * content) before ffv_interpolate or ffv_submit on an FP8 net; may be called
+ * again to recalibrate. Errors: FFV_ERR_ARG, FFV_ERR_STATE (not an FP8 net),
+ * FFV_ERR_OOM, FFV_ERR_DEVICE.
+ */
+ffv_status ffv_calibrate(ffv_net* net, const ffv_pair* pair, float t);
 
 /* ---------------------------------------------------------------------- */
 /* Serving (enabled when ffv_opts.hbm_budget_bytes > 0)                     */
@@ -196,11 +244,16 @@ ffv_status ffv_kernel_stats(ffv_net* net, const char* name, int64_t* launches, d
  *   y:      DEVICE float32 planar [n][cout][ho][wo], ho = (h-1)/stride+1
  *           (conv) or 2h (transposed)
  * precision: FFV_FP32 or FFV_BF16 (inputs and weights rounded to bf16, fp32
- * accumulation and output). Allocates temporaries; synchronises `stream`.
+ * accumulation and output). n_tile (0 = the layer's default, else 256, 128,
+ * 64 or 32 output channels per workgroup) and tile_w (0 = default, else the
+ * width of the 256-pixel block of a workgroup, a divisor of 256) pick the
+ * kernel variant, as autotuning does; every choice gives the same result.
+ * Allocates temporaries; synchronises `stream`.
  */
 ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, int32_t cin, int32_t h,
                        int32_t w, const float* weight, const float* bias, int32_t cout,
-                       int32_t stride, int32_t transposed, int32_t relu, float* y, void* stream);
+                       int32_t stride, int32_t transposed, int32_t relu, int32_t n_tile,
+                       int32_t tile_w, float* y, void* stream);
 
 #ifdef __cplusplus
 }

@@ -29,6 +29,24 @@ ffv_status from(const ffv::Status& s) {
   return fail(s.code, s.msg);
 }
 
+// Shared argument checks of ffv_interpolate and ffv_autotune.
+ffv_status check_call(ffv_net* net, const ffv_pair* views, int32_t n_pairs, const float* t,
+                      int32_t n_t, float* out) {
+  if (!net || !views || !t || !out) return fail(FFV_ERR_ARG, "null argument");
+  if (n_pairs <= 0 || n_t <= 0) return fail(FFV_ERR_ARG, "n_pairs and n_t must be positive");
+  const int H = views[0].height, W = views[0].width;
+  if (H < 2 || W < 2) return fail(FFV_ERR_ARG, "height and width must be >= 2");
+  if ((long)H * W > (1L << 28)) return fail(FFV_ERR_ARG, "image too large");
+  for (int i = 0; i < n_pairs; ++i) {
+    if (!views[i].left || !views[i].right) return fail(FFV_ERR_ARG, "null image pointer");
+    if (views[i].height != H || views[i].width != W)
+      return fail(FFV_ERR_ARG, "all pairs of one call must share height and width");
+  }
+  for (int j = 0; j < n_t; ++j)
+    if (!(t[j] >= 0.f && t[j] <= 1.f)) return fail(FFV_ERR_ARG, "t must lie in [0, 1]");
+  return FFV_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -39,6 +57,7 @@ void ffv_default_opts(ffv_opts* o) {
   o->abi_version = FFV_ABI_VERSION;
   o->precision = FFV_FP32;
   o->device = 0;
+  o->graphs = 1;
   o->stream = nullptr;
   o->workspace_bytes = 0;
   o->hbm_budget_bytes = 0;
@@ -50,13 +69,14 @@ ffv_status ffv_create_net(const char* weights_path, const ffv_opts* opts, ffv_ne
   if (!weights_path || !opts || !out) return fail(FFV_ERR_ARG, "null argument");
   *out = nullptr;
   if (opts->abi_version != FFV_ABI_VERSION) return fail(FFV_ERR_ARG, "ABI version mismatch");
-  if (opts->precision == FFV_FP8_E4M3) return fail(FFV_ERR_ARG, "FP8 precision is not built");
-  if (opts->precision != FFV_FP32 && opts->precision != FFV_BF16)
+  if (opts->precision != FFV_FP32 && opts->precision != FFV_BF16 &&
+      opts->precision != FFV_FP8_E4M3)
     return fail(FFV_ERR_ARG, "unknown precision");
   try {
     ffv_net* n = new ffv_net();
     ffv::Status s = n->net.init(weights_path, opts->precision, opts->device,
                                 (hipStream_t)opts->stream, opts->workspace_bytes);
+    if (s.good()) n->net.set_graphs(opts->graphs != 0);
     if (s.good() && opts->hbm_budget_bytes > 0)
       s = n->net.start_serving(opts->hbm_budget_bytes, opts->tick_ms, opts->max_batch_views);
     if (!s.good()) {
@@ -75,20 +95,55 @@ ffv_status ffv_create_net(const char* weights_path, const ffv_opts* opts, ffv_ne
 
 void ffv_destroy_net(ffv_net* net) { delete net; }
 
+ffv_status ffv_autotune(ffv_net* net, const ffv_pair* views, int32_t n_pairs, const float* t,
+                        int32_t n_t, float* out, int32_t* n_tuned) {
+  const ffv_status c = check_call(net, views, n_pairs, t, n_t, out);
+  if (c != FFV_OK) return c;
+  try {
+    std::vector<const float*> l(n_pairs), r(n_pairs);
+    for (int i = 0; i < n_pairs; ++i) {
+      l[i] = views[i].left;
+      r[i] = views[i].right;
+    }
+    int n = 0;
+    const ffv_status st = from(net->net.autotune(l.data(), r.data(), n_pairs, views[0].height,
+                                                 views[0].width, t, n_t, out, &n));
+    if (n_tuned) *n_tuned = n;
+    return st;
+  } catch (const std::bad_alloc&) {
+    return fail(FFV_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(FFV_ERR_DEVICE, e.what());
+  }
+}
+
+ffv_status ffv_save_tuning(ffv_net* net, const char* path) {
+  if (!net || !path) return fail(FFV_ERR_ARG, "null argument");
+  try {
+    return from(net->net.save_tuning(path));
+  } catch (const std::exception& e) {
+    return fail(FFV_ERR_DEVICE, e.what());
+  }
+}
+
+ffv_status ffv_load_tuning(ffv_net* net, const char* path, int32_t* n_loaded) {
+  if (!net || !path) return fail(FFV_ERR_ARG, "null argument");
+  try {
+    int n = 0;
+    const ffv_status st = from(net->net.load_tuning(path, &n));
+    if (n_loaded) *n_loaded = n;
+    return st;
+  } catch (const std::exception& e) {
+    return fail(FFV_ERR_DEVICE, e.what());
+  }
+}
+
 ffv_status ffv_interpolate(ffv_net* net, const ffv_pair* views, int32_t n_pairs, const float* t,
                            int32_t n_t, float* out) {
-  if (!net || !views || !t || !out) return fail(FFV_ERR_ARG, "null argument");
-  if (n_pairs <= 0 || n_t <= 0) return fail(FFV_ERR_ARG, "n_pairs and n_t must be positive");
+  const ffv_status c = check_call(net, views, n_pairs, t, n_t, out);
+  if (c != FFV_OK) return c;
   const int H = views[0].height, W = views[0].width;
-  if (H < 2 || W < 2) return fail(FFV_ERR_ARG, "height and width must be >= 2");
-  if ((long)H * W > (1L << 28)) return fail(FFV_ERR_ARG, "image too large");
-  for (int i = 0; i < n_pairs; ++i) {
-    if (!views[i].left || !views[i].right) return fail(FFV_ERR_ARG, "null image pointer");
-    if (views[i].height != H || views[i].width != W)
-      return fail(FFV_ERR_ARG, "all pairs of one call must share height and width");
-  }
-  for (int j = 0; j < n_t; ++j)
-    if (!(t[j] >= 0.f && t[j] <= 1.f)) return fail(FFV_ERR_ARG, "t must lie in [0, 1]");
+  if (n_pairs <= 0 || n_t <= 0) return fail(FFV_ERR_ARG, "n_pairs and n_t must be positive");
   try {
     std::vector<const float*> l(n_pairs), r(n_pairs);
     for (int i = 0; i < n_pairs; ++i) {
@@ -104,6 +159,17 @@ ffv_status ffv_interpolate(ffv_net* net, const ffv_pair* views, int32_t n_pairs,
 }
 
 const char* ffv_last_error(void) { return g_last_error.c_str(); }
+
+ffv_status ffv_calibrate(ffv_net* net, const ffv_pair* pair, float t) {
+  if (!net || !pair || !pair->left || !pair->right) return fail(FFV_ERR_ARG, "null argument");
+  if (pair->height < 2 || pair->width < 2) return fail(FFV_ERR_ARG, "height and width must be >= 2");
+  if (!(t >= 0.f && t <= 1.f)) return fail(FFV_ERR_ARG, "t must lie in [0, 1]");
+  try {
+    return from(net->net.calibrate(pair->left, pair->right, pair->height, pair->width, t));
+  } catch (const std::exception& e) {
+    return fail(FFV_ERR_DEVICE, e.what());
+  }
+}
 
 ffv_status ffv_register_camera(ffv_net* net, int32_t cam_id, const float* image, int32_t height,
                                int32_t width) {
@@ -203,12 +269,16 @@ ffv_status ffv_kernel_stats(ffv_net* net, const char* name, int64_t* launches, d
 extern "C" ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, int32_t cin,
                                   int32_t h, int32_t w, const float* weight, const float* bias,
                                   int32_t cout, int32_t stride, int32_t transposed, int32_t relu,
-                                  float* y, void* stream) {
+                                  int32_t n_tile, int32_t tile_w, float* y, void* stream) {
   using namespace ffv;
   if (!x || !weight || !bias || !y) return fail(FFV_ERR_ARG, "null argument");
   if (precision != FFV_FP32 && precision != FFV_BF16) return fail(FFV_ERR_ARG, "precision");
   if (n <= 0 || cin <= 0 || h <= 0 || w <= 0 || cout <= 0) return fail(FFV_ERR_ARG, "sizes");
   if (!transposed && stride != 1 && stride != 2) return fail(FFV_ERR_ARG, "stride");
+  if (n_tile != 0 && n_tile != 32 && n_tile != 64 && n_tile != 128 && n_tile != 256)
+    return fail(FFV_ERR_ARG, "n_tile must be 0, 32, 64, 128 or 256");
+  if (tile_w < 0 || tile_w > 256 || (tile_w > 0 && 256 % tile_w != 0))
+    return fail(FFV_ERR_ARG, "tile_w must be 0 or divide 256");
   const DType dt = precision == FFV_FP32 ? DType::F32 : DType::BF16;
   hipStream_t s = (hipStream_t)stream;
   Layer L;
@@ -262,6 +332,7 @@ extern "C" ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, 
     a.K_pad = L.K_pad;
     a.cout = cout;
     a.cout_pad = L.cout_pad;
+    a.n_rows = L.rows;
     a.n_img = n;
     a.stride = L.transposed ? 1 : stride;
     a.transposed = L.mode;
@@ -270,8 +341,13 @@ extern "C" ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, 
     a.accumulate = 0;
     a.taps = L.mode == 1 ? 4 : 9;
     a.zero = zr;
-    a.tile_w = conv_tile_width(a.Ho, a.Wo);
-    err = launch_conv(dt, L.tile, a, s);
+    a.tile_w = tile_w > 0 ? tile_w : conv_tile_width(a.Ho, a.Wo);
+    ConvTile tile = L.tile;
+    if (n_tile == 256) tile = ConvTile::N256;
+    if (n_tile == 128) tile = ConvTile::N128;
+    if (n_tile == 64) tile = ConvTile::N64;
+    if (n_tile == 32) tile = ConvTile::N32;
+    err = launch_conv(dt, tile, a, s);
   }
   for (int i = 0; err == hipSuccess && i < n; ++i)
     err = launch_extract((const float*)yo + (size_t)i * ho * wo * cout, DType::F32, cout, cout,

@@ -9,13 +9,18 @@
 namespace ffv {
 
 typedef __bf16 bf16;
+// fp8 e4m3 (OCP: bias 7, max 448, no infinities) as stored bytes
+struct f8 {
+  uint8_t v;
+};
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(8))) int i32x8;
 
-enum class DType : int { F32 = 0, BF16 = 1 };
+enum class DType : int { F32 = 0, BF16 = 1, FP8 = 2 };
 
-inline size_t dtype_size(DType t) { return t == DType::F32 ? 4 : 2; }
+inline size_t dtype_size(DType t) { return t == DType::F32 ? 4 : (t == DType::BF16 ? 2 : 1); }
 
 // One implicit-GEMM convolution launch: C[m][n] = sum_k A[m][k] * B[n][k].
 //   m: output pixel of the GEMM grid (image, oy, ox), M = n_img * Ho * Wo
@@ -40,14 +45,18 @@ struct ConvArgs {
   int K;                // taps * cin_pad
   int K_pad;            // K rounded up to the K tile
   int cout;             // real output channels
-  int cout_pad;         // rows per phase in the packed weights
+  int cout_pad;         // rows per phase in the packed weights (a multiple of 256)
+  int n_rows;           // GEMM N: cout, or 4 * cout phase-merged; grid y = ceil(n_rows / BN)
   int n_img;
   int stride;           // 1 or 2 (conv); 1 for transposed
   int transposed;       // 0: 3x3 conv; 1: 4x4 s2 transposed, one output phase per
                         // blockIdx.z; 2: 4x4 s2 transposed, phase-merged (n = phase*cout + o)
   int relu;
-  int out_f32;          // 1: float output, 0: activation dtype
+  int out_f32;          // 1: float output, 0: activation dtype (or fp8, see out_scale)
   int accumulate;       // 1: add into the existing float output
+  const float* w_scale;   // per output channel, multiplies the accumulator (fp8 weights); or null
+  const float* out_scale; // per output channel: store fp8(value * out_scale[o]); or null
+  float* amax;            // per output channel max |value| (calibration); or null
   int taps;             // taps in K (9, or 4 for one transposed phase)
   int tile_w;           // width of the 2-D pixel block of an M tile (divides the M tile)
   const void* zero;     // >= 16 bytes of zeros (read for taps outside the image)

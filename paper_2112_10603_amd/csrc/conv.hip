@@ -25,7 +25,7 @@ hipError_t launch_t(ConvTile tile, const ConvArgs& a, hipStream_t s) {
 
 }  // namespace
 
-int conv_k_step(DType dt) { return dt == DType::F32 ? 32 : 64; }
+int conv_k_step(DType dt) { return dt == DType::F32 ? 32 : (dt == DType::BF16 ? 64 : 128); }
 
 int conv_tile_width(int Ho, int Wo) {
   int best = 16;
@@ -44,6 +44,7 @@ int conv_tile_width(int Ho, int Wo) {
 hipError_t launch_conv(DType dt, ConvTile tile, const ConvArgs& a, hipStream_t s) {
   if (a.n_img <= 0 || a.Ho <= 0 || a.Wo <= 0) return hipSuccess;
   if (dt == DType::F32) return launch_t<float>(tile, a, s);
+  if (dt == DType::FP8) return launch_t<f8>(tile, a, s);
   return launch_t<bf16>(tile, a, s);
 }
 

@@ -85,14 +85,33 @@ __device__ inline void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
+// 32 bytes = 32 fp8 k-values per lane (two chunks): one 32x32x64 MFMA
+// (f8f6f4 with both operands e4m3 and unit block scales).
+__device__ inline void mfma_f8(f32x16& acc, const uint4& a0, const uint4& a1, const uint4& b0,
+                               const uint4& b1) {
+  const i32x8 av = {(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w,
+                    (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
+  const i32x8 bv = {(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w,
+                    (int)b1.x, (int)b1.y, (int)b1.z, (int)b1.w};
+  acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc, 0, 0, 0, 127, 0, 127);
+}
+
+// float -> fp8 e4m3 byte: saturate to +-448, round to nearest even
+__device__ inline uint8_t to_f8(float v) {
+  v = fminf(fmaxf(v, -448.f), 448.f);
+  return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, v, 0, false) & 0xff);
+}
+
 template <typename T>
-__device__ inline void store_out(const ConvArgs& a, long off, float v) {
+__device__ inline void store_out(const ConvArgs& a, long off, int o, float v) {
   if (a.out_f32) {
-    float* o = reinterpret_cast<float*>(a.out) + off;
-    if (a.accumulate) v += *o;
-    *o = v;
+    float* p = reinterpret_cast<float*>(a.out) + off;
+    if (a.accumulate) v += *p;
+    *p = v;
+  } else if (a.out_scale) {
+    reinterpret_cast<uint8_t*>(a.out)[off] = to_f8(v * a.out_scale[o]);
   } else {
-    reinterpret_cast<T*>(a.out)[off] = (T)v;
+    reinterpret_cast<bf16*>(a.out)[off] = (bf16)v;
   }
 }
 
@@ -254,18 +273,41 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
 
   auto compute = [&](int buf) {
+    if constexpr (sizeof(T) == 1) {
+      // fp8: a lane half's CH/2 chunks feed CH/4 MFMAs of two chunks each
 #pragma unroll
-    for (int s = 0; s < CH / 2; ++s) {
-      const int ch = lhalf * (CH / 2) + s;
-      uint4 fa[FM], fb[FN];
+      for (int s = 0; s < CH / 4; ++s) {
+        const int ch = lhalf * (CH / 2) + 2 * s;
+        uint4 fa[FM][2], fb[FN][2];
 #pragma unroll
-      for (int i = 0; i < FM; ++i) fa[i] = As[buf][C::swz(wm * TM + i * 32 + lrow, ch)];
+        for (int i = 0; i < FM; ++i) {
+          fa[i][0] = As[buf][C::swz(wm * TM + i * 32 + lrow, ch)];
+          fa[i][1] = As[buf][C::swz(wm * TM + i * 32 + lrow, ch + 1)];
+        }
 #pragma unroll
-      for (int j = 0; j < FN; ++j) fb[j] = Bs[buf][C::swz(wn * TN + j * 32 + lrow, ch)];
+        for (int j = 0; j < FN; ++j) {
+          fb[j][0] = Bs[buf][C::swz(wn * TN + j * 32 + lrow, ch)];
+          fb[j][1] = Bs[buf][C::swz(wn * TN + j * 32 + lrow, ch + 1)];
+        }
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) mfma_chunk<T>(acc[i][j], fa[i], fb[j]);
+          for (int j = 0; j < FN; ++j) mfma_f8(acc[i][j], fa[i][0], fa[i][1], fb[j][0], fb[j][1]);
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < CH / 2; ++s) {
+        const int ch = lhalf * (CH / 2) + s;
+        uint4 fa[FM], fb[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) fa[i] = As[buf][C::swz(wm * TM + i * 32 + lrow, ch)];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) fb[j] = Bs[buf][C::swz(wn * TN + j * 32 + lrow, ch)];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) mfma_chunk<T>(acc[i][j], fa[i], fb[j]);
+      }
     }
   };
 
@@ -322,13 +364,17 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
         col = ((long)(ph >> 1) * a.Wout + (ph & 1)) * a.out_ld + o;
       }
       const float bn = a.bias[o];
+      const float ws = a.w_scale ? a.w_scale[o] : 1.f;
+      float amax = 0.f;
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         if (!row_ok[e]) continue;
-        float v = acc[i][j][e] + bn;
+        float v = acc[i][j][e] * ws + bn;
         if (a.relu) v = fmaxf(v, 0.f);
-        store_out<T>(a, off_row[e] + col, v);
+        amax = fmaxf(amax, fabsf(v));
+        store_out<T>(a, off_row[e] + col, o, v);
       }
+      if (a.amax) atomicMax(reinterpret_cast<unsigned*>(a.amax) + o, __float_as_uint(amax));
     }
   }
 }
@@ -337,13 +383,15 @@ template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES, int SW
 hipError_t launch_variant(const ConvArgs& a, hipStream_t s) {
   using C = Conv<T, BM, BN, WM, WN, KB, STAGES, SWZ>;
   const int phases = a.transposed == 1 ? 4 : 1;
-  if (a.K_pad % C::BK != 0 || a.cin_pad % C::VEC != 0 || a.cout_pad % BN != 0 ||
-      a.in_ld % C::VEC != 0 || a.tile_w <= 0 || BM % a.tile_w != 0)
+  const int n_tiles = (a.n_rows + BN - 1) / BN;
+  // every B row a tile reads (n_tiles * BN of them) must exist in the packed weights
+  if (a.K_pad % C::BK != 0 || a.cin_pad % C::VEC != 0 || a.n_rows <= 0 ||
+      n_tiles * BN > a.cout_pad || a.in_ld % C::VEC != 0 || a.tile_w <= 0 || BM % a.tile_w != 0)
     return hipErrorInvalidValue;
   const long tiles = (long)a.n_img * ((a.Ho + BM / a.tile_w - 1) / (BM / a.tile_w)) *
                      ((a.Wo + a.tile_w - 1) / a.tile_w);
   if (tiles > 0x7fffffffL) return hipErrorInvalidValue;
-  dim3 grid((unsigned)tiles, (unsigned)(a.cout_pad / BN), phases);
+  dim3 grid((unsigned)tiles, (unsigned)n_tiles, phases);
   hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES, SWZ>), grid, dim3(C::NT), 0, s, a);
   return hipGetLastError();
 }

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <fstream>
 #include <sstream>
@@ -179,16 +180,20 @@ void plan_layer(Layer& L) {
   const int bn = n > 128 ? 256 : (n > 64 ? 128 : (n > 32 ? 64 : 32));
   L.tile = bn == 256 ? ConvTile::N256
                      : (bn == 128 ? ConvTile::N128 : (bn == 64 ? ConvTile::N64 : ConvTile::N32));
-  L.cout_pad = round_up(n, bn);
+  L.rows = n;
+  // rows padded to the widest N tile, so any tile width can run the layer
+  L.cout_pad = round_up(n, 256);
 }
 
-std::vector<uint8_t> pack_layer(const Layer& L, DType dt) {
+// Weights (file layout w_file) rearranged as the conv kernel reads them, in
+// float: [phase][cout_pad][k_pad] with the kernel's K order for K step bk.
+static std::vector<float> pack_layer_f(const Layer& L, int bk, int k_pad,
+                                       const std::vector<float>& w_file) {
   const int phases = L.mode == 1 ? 4 : 1;
   const int taps = L.mode == 1 ? 4 : 9;
-  const size_t n = (size_t)phases * L.cout_pad * L.K_pad;
+  const size_t n = (size_t)phases * L.cout_pad * k_pad;
   // K position of (tap, channel): channel-slice major when the channel count
   // is a multiple of the kernel's K step (as the kernel walks K), else tap major.
-  const int bk = conv_k_step(dt);
   const bool slice_major = L.cin_pad % bk == 0;
   auto kpos = [&](int tap, int c) {
     if (!slice_major) return tap * L.cin_pad + c;
@@ -198,9 +203,9 @@ std::vector<uint8_t> pack_layer(const Layer& L, DType dt) {
   if (L.mode == 0) {
     // tap = dy*3 + dx  <-  w[o][c][dy][dx]
     for (int o = 0; o < L.cout; ++o) {
-      float* row = &p[(size_t)o * L.K_pad];
+      float* row = &p[(size_t)o * k_pad];
       for (int c = 0; c < L.cin; ++c)
-        for (int tap = 0; tap < 9; ++tap) row[kpos(tap, c)] = L.w_host[((size_t)o * L.cin + c) * 9 + tap];
+        for (int tap = 0; tap < 9; ++tap) row[kpos(tap, c)] = w_file[((size_t)o * L.cin + c) * 9 + tap];
     }
   } else if (L.mode == 1) {
     // phase (py, px), tap (ty, tx) reads input (a + py - ty, b + px - tx) with
@@ -208,12 +213,12 @@ std::vector<uint8_t> pack_layer(const Layer& L, DType dt) {
     for (int ph = 0; ph < 4; ++ph) {
       const int py = ph >> 1, px = ph & 1;
       for (int o = 0; o < L.cout; ++o) {
-        float* row = &p[((size_t)ph * L.cout_pad + o) * L.K_pad];
+        float* row = &p[((size_t)ph * L.cout_pad + o) * k_pad];
         for (int c = 0; c < L.cin; ++c)
           for (int ty = 0; ty < 2; ++ty)
             for (int tx = 0; tx < 2; ++tx) {
               const int ky = 1 - py + 2 * ty, kx = 1 - px + 2 * tx;
-              row[kpos(ty * 2 + tx, c)] = L.w_host[(((size_t)c * L.cout + o) * 4 + ky) * 4 + kx];
+              row[kpos(ty * 2 + tx, c)] = w_file[(((size_t)c * L.cout + o) * 4 + ky) * 4 + kx];
             }
       }
     }
@@ -224,7 +229,7 @@ std::vector<uint8_t> pack_layer(const Layer& L, DType dt) {
     for (int ph = 0; ph < 4; ++ph) {
       const int py = ph >> 1, px = ph & 1;
       for (int o = 0; o < L.cout; ++o) {
-        float* row = &p[((size_t)ph * L.cout + o) * L.K_pad];
+        float* row = &p[((size_t)ph * L.cout + o) * k_pad];
         for (int dy = -1; dy <= 1; ++dy)
           for (int dx = -1; dx <= 1; ++dx) {
             const int ty = py - dy, tx = px - dx;
@@ -232,13 +237,46 @@ std::vector<uint8_t> pack_layer(const Layer& L, DType dt) {
             const int ky = 1 - py + 2 * ty, kx = 1 - px + 2 * tx;
             const int tap = (dy + 1) * 3 + (dx + 1);
             for (int c = 0; c < L.cin; ++c)
-              row[kpos(tap, c)] = L.w_host[(((size_t)c * L.cout + o) * 4 + ky) * 4 + kx];
+              row[kpos(tap, c)] = w_file[(((size_t)c * L.cout + o) * 4 + ky) * 4 + kx];
           }
       }
     }
   }
+  return p;
+}
+
+// float -> fp8 e4m3 (OCP: bias 7, max 448, no infinities) byte, saturating,
+// round to nearest even.
+static uint8_t f2f8(float v) {
+  uint8_t sign = std::signbit(v) ? 0x80 : 0;
+  float a = std::fabs(v);
+  if (!(a == a)) return 0x7f;  // NaN
+  if (a >= 448.f) return sign | 0x7e;
+  if (a < std::ldexp(1.f, -10)) return sign;  // below half the smallest subnormal
+  int e = (int)std::floor(std::log2(a));
+  if (e < -6) {  // subnormal: multiples of 2^-9
+    const float q = std::nearbyint(a * 512.f);
+    if (q >= 8.f) return sign | 0x08;
+    return sign | (uint8_t)q;
+  }
+  float m = a / std::ldexp(1.f, e) - 1.f;  // [0, 1)
+  float q = std::nearbyint(m * 8.f);
+  if (q >= 8.f) {
+    q = 0.f;
+    e += 1;
+  }
+  if (e > 8 || (e == 8 && q > 6.f)) return sign | 0x7e;
+  return sign | (uint8_t)((e + 7) << 3) | (uint8_t)q;
+}
+
+std::vector<uint8_t> pack_layer(const Layer& L, DType dt) {
+  const size_t n = (size_t)(L.mode == 1 ? 4 : 1) * L.cout_pad * L.K_pad;
+  std::vector<float> p = pack_layer_f(L, conv_k_step(dt), L.K_pad, L.w_host);
   std::vector<uint8_t> bytes;
-  if (dt == DType::F32) {
+  if (dt == DType::FP8) {
+    bytes.resize(n);
+    for (size_t i = 0; i < n; ++i) bytes[i] = f2f8(p[i]);
+  } else if (dt == DType::F32) {
     bytes.resize(n * 4);
     std::memcpy(bytes.data(), p.data(), n * 4);
   } else {
@@ -269,9 +307,12 @@ Net::~Net() {
   server_.reset();
   if (device_ >= 0) hipSetDevice(device_);
   if (stream_) hipStreamSynchronize(stream_);
+  drop_graphs();
   for (auto& kv : layers_) {
-    if (kv.second.w_dev) hipFree(kv.second.w_dev);
-    if (kv.second.b_dev) hipFree(kv.second.b_dev);
+    Layer& L = kv.second;
+    for (void* p : {(void*)L.w_dev, (void*)L.b_dev, L.w8_dev, (void*)L.w8_scale, (void*)L.out_scale,
+                    (void*)L.amax})
+      if (p) hipFree(p);
   }
   if (ws_) hipFree(ws_);
   if (zero_) hipFree(zero_);
@@ -297,9 +338,9 @@ Status Net::check(hipError_t e, const char* what) const {
 
 Status Net::init(const std::string& path, int precision, int device, hipStream_t stream,
                  size_t workspace_cap) {
-  if (precision != 0 && precision != 1)
-    return Status::err(-1, "precision not supported (FP32 = 0 and BF16 = 1 are built)");
+  if (precision < 0 || precision > 2) return Status::err(-1, "unknown precision");
   dt_ = precision == 0 ? DType::F32 : DType::BF16;
+  fp8_ = precision == 2;
   device_ = device;
   ws_cap_ = workspace_cap ? workspace_cap : (size_t)16 << 30;
   WeightsFile wf;
@@ -410,10 +451,40 @@ ViewPlan Net::view_plan(const Geo& g, int n_view) const {
   return p;
 }
 
+void Net::drop_graphs() {
+  for (auto& kv : graph_cache_) {
+    hipGraphExecDestroy(kv.second.exec);
+    for (auto& pe : kv.second.prof) {
+      evt_pool_.push_back(pe.a);
+      evt_pool_.push_back(pe.b);
+    }
+  }
+  graph_cache_.clear();
+}
+
+void Net::add_stat(const PendingEvt& pe) {
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, pe.a, pe.b);
+  KernelStat& ks = stats_[pe.cls];
+  ks.launches += 1;
+  ks.ms += ms;
+  ks.work += pe.work;
+}
+
+void Net::set_graphs(bool on) {
+  std::lock_guard<std::mutex> lk(call_mu_);
+  graphs_ = on;
+  if (!on) {
+    if (stream_) hipStreamSynchronize(stream_);
+    drop_graphs();
+  }
+}
+
 Status Net::ensure_workspace(size_t bytes) {
   if (bytes <= ws_bytes_) return Status::ok();
   if (ws_) {
     hipStreamSynchronize(stream_);
+    drop_graphs();  // they address the old workspace
     hipFree(ws_);
     ws_ = nullptr;
     ws_bytes_ = 0;
@@ -471,14 +542,17 @@ Status Net::kernel_stats(const std::string& name, long* launches, double* ms, do
 
 Status Net::conv(const Exec& x, const Layer& L, const void* in, int in_ld, long in_img_stride,
                  int Hi, int Wi, int n_img, void* out, int out_ld, long out_img_stride,
-                 bool out_f32, bool accumulate, bool relu) {
+                 bool out_f32, bool accumulate, bool relu, bool in_fp8, bool out_fp8) {
   ConvArgs a{};
   a.in = in;
   a.in_img_stride = in_img_stride;
   a.in_ld = in_ld;
   a.Hi = Hi;
   a.Wi = Wi;
-  a.wgt = L.w_dev;
+  a.wgt = in_fp8 ? L.w8_dev : L.w_dev;
+  a.w_scale = in_fp8 ? L.w8_scale : nullptr;
+  a.out_scale = out_fp8 ? L.out_scale : nullptr;
+  a.amax = calibrating_ ? L.amax : nullptr;
   a.bias = L.b_dev;
   a.out = out;
   a.out_img_stride = out_img_stride;
@@ -496,9 +570,10 @@ Status Net::conv(const Exec& x, const Layer& L, const void* in, int in_ld, long 
   }
   a.cin_pad = L.cin_pad;
   a.K = L.K;
-  a.K_pad = L.K_pad;
+  a.K_pad = in_fp8 ? round_up(L.K, 128) : L.K_pad;
   a.cout = L.cout;
   a.cout_pad = L.cout_pad;
+  a.n_rows = L.rows;
   a.n_img = n_img;
   a.stride = L.transposed ? 1 : L.stride;
   a.transposed = L.mode;
@@ -508,7 +583,19 @@ Status Net::conv(const Exec& x, const Layer& L, const void* in, int in_ld, long 
   a.taps = L.mode == 1 ? 4 : 9;
   a.zero = zero_;
   a.tile_w = conv_tile_width(a.Ho, a.Wo);
-  if (in_ld < L.cin_pad || in_ld % 8 != 0) return Status::err(-4, "conv input stride");
+  ConvTile tile = L.tile;
+  const DType kdt = in_fp8 ? DType::FP8 : dt_;
+  if (!tuned_.empty() || recording_) {
+    const TuneKey key{L.name, in_fp8 ? 1 : 0, a.Ho, a.Wo, n_img};
+    auto it = tuned_.find(key);
+    if (it != tuned_.end()) {
+      tile = it->second.tile;
+      a.tile_w = it->second.tile_w;
+    }
+    if (recording_) recs_.push_back(TuneRec{key, a, kdt});
+  }
+  if (in_ld < L.cin_pad || in_ld % (in_fp8 ? 16 : 8) != 0) return Status::err(-4, "conv input stride");
+  if ((in_fp8 && !L.w8_dev) || (out_fp8 && !L.out_scale)) return Status::err(-7, "fp8 layer not quantised");
   const double flops = 2.0 * n_img * (double)a.Hout * a.Wout * L.cout * L.cin *
                        (L.transposed ? 4.0 : 9.0);
   const char* cls = L.transposed ? "convT"
@@ -517,7 +604,7 @@ Status Net::conv(const Exec& x, const Layer& L, const void* in, int in_ld, long 
                                         ? "conv256"
                                         : "conv");
   prof_begin(x);
-  Status st = check(launch_conv(dt_, L.tile, a, x.s), L.name.c_str());
+  Status st = check(launch_conv(kdt, tile, a, x.s), L.name.c_str());
   prof_end(x, cls, flops);
   return st;
 }
@@ -576,14 +663,18 @@ Status Net::build_cameras(const Exec& x, const Geo& g, const float* const* src_d
 }
 
 Status Net::run_views(const Exec& x, const ViewPlan& p, const CamDev* cams,
-                      const ViewDesc* views_host, int nv) {
+                      const ViewDesc* views_in, int nv, bool views_on_device) {
   const Geo& g = p.g;
   const long P = g.P;
   const int B = base_width_;
   const size_t e = dtype_size(dt_);
-  ViewDesc* views = (ViewDesc*)x.at(p.views);
-  FFV_TRY(check(hipMemcpyAsync(views, views_host, sizeof(ViewDesc) * nv, hipMemcpyHostToDevice, x.s),
-                "copy views"));
+  const ViewDesc* views = views_in;
+  if (!views_on_device) {
+    ViewDesc* slot = (ViewDesc*)x.at(p.views);
+    FFV_TRY(check(hipMemcpyAsync(slot, views_in, sizeof(ViewDesc) * nv, hipMemcpyHostToDevice, x.s),
+                  "copy views"));
+    views = slot;
+  }
   const int tp = t_plane_ ? 1 : 0;
 
   // stage 0 input
@@ -610,23 +701,26 @@ Status Net::run_views(const Exec& x, const ViewPlan& p, const CamDev* cams,
     }
     const int h1 = h / 2, w1 = w / 2, h2 = h / 4, w2 = w / 4;
     const int C1 = 4 * B, C2 = 8 * B;
+    // FP8 nets keep the VIBlock's inner activations (a1, the 256-channel
+    // chain, a9) in fp8; conv1 quantises its output, convT2 reads fp8.
+    const bool q = vib_fp8();
     FFV_TRY(conv(x, L("conv1"), x.at(p.xin), in_ld, Ps * in_ld, h, w, nv, x.at(p.a1), C1,
-                 (long)h1 * w1 * C1, false, false, true));
+                 (long)h1 * w1 * C1, false, false, true, false, q));
     FFV_TRY(conv(x, L("conv2"), x.at(p.a1), C1, (long)h1 * w1 * C1, h1, w1, nv, x.at(p.bA), C2,
-                 (long)h2 * w2 * C2, false, false, true));
+                 (long)h2 * w2 * C2, false, false, true, q, q));
     void* cur = x.at(p.bA);
     void* nxt = x.at(p.bB);
     for (int i = 3; i <= 8; ++i) {
       char suf[16];
       snprintf(suf, sizeof suf, "conv%d", i);
       FFV_TRY(conv(x, L(suf), cur, C2, (long)h2 * w2 * C2, h2, w2, nv, nxt, C2, (long)h2 * w2 * C2,
-                   false, false, true));
+                   false, false, true, q, q));
       std::swap(cur, nxt);
     }
     FFV_TRY(conv(x, L("convT1"), cur, C2, (long)h2 * w2 * C2, h2, w2, nv, x.at(p.a1), C1,
-                 (long)h1 * w1 * C1, false, false, true));
+                 (long)h1 * w1 * C1, false, false, true, q, q));
     FFV_TRY(conv(x, L("convT2"), x.at(p.a1), C1, (long)h1 * w1 * C1, h1, w1, nv, x.at(p.FM[s]), 8,
-                 Ps * 8, true, s > 0, false));
+                 Ps * 8, true, s > 0, false, q, false));
   }
 
   // final warp + blend, U-Net input
@@ -717,6 +811,12 @@ Status Net::run_views(const Exec& x, const ViewPlan& p, const CamDev* cams,
 Status Net::interpolate(const float* const* left, const float* const* right, int n_pairs, int H,
                         int W, const float* t, int n_t, float* out) {
   std::lock_guard<std::mutex> lk(call_mu_);
+  return interpolate_locked(left, right, n_pairs, H, W, t, n_t, out);
+}
+
+Status Net::interpolate_locked(const float* const* left, const float* const* right, int n_pairs,
+                               int H, int W, const float* t, int n_t, float* out) {
+  if (!ready() && !calibrating_) return Status::err(-7, "FP8 net needs ffv_calibrate first");
   FFV_TRY(check(hipSetDevice(device_), "hipSetDevice"));
   const Geo g = Geo::of(H, W);
 
@@ -740,7 +840,8 @@ Status Net::interpolate(const float* const* left, const float* const* right, int
   const CamPlan cp = cam_plan(g);
   const size_t cam_region = align_up(cp.bytes * n_cam, 256);
   const size_t ctmp_region = align_up(cp.ctmp * n_cam, 256);
-  const size_t tab_region = align_up(sizeof(CamDev) * n_cam + sizeof(void*) * n_cam, 256);
+  const size_t tab_region = align_up(sizeof(CamDev) * n_cam + sizeof(void*) * n_cam, 256) +
+                            align_up(sizeof(ViewDesc) * n_view_total, 256);
   const size_t fixed = cam_region + ctmp_region + tab_region;
   const size_t per_view = view_plan(g, 2).total - view_plan(g, 1).total;
   int chunk = n_view_total;
@@ -770,7 +871,6 @@ Status Net::interpolate(const float* const* left, const float* const* right, int
   FFV_TRY(check(hipMemcpyAsync(src_tab, cams.data(), sizeof(void*) * n_cam, hipMemcpyHostToDevice,
                                stream_),
                 "copy image table"));
-  FFV_TRY(build_cameras(x, g, src_tab, n_cam, blocks.data(), ctmp));
 
   std::vector<ViewDesc> vd(n_view_total);
   for (int i = 0; i < n_pairs; ++i)
@@ -782,24 +882,76 @@ Status Net::interpolate(const float* const* left, const float* const* right, int
       d.t = t[j];
       d.out = out + ((size_t)i * n_t + j) * 3 * (size_t)H * W;
     }
+  // Graph replay needs every per-call value in device tables: the camera
+  // and image tables above, and here all views' descriptors.
+  const bool use_graph = graphs_ && !debug_ && !calibrating_ && !recording_;
+  ViewDesc* view_tab = (ViewDesc*)(base + cam_region + ctmp_region +
+                                   align_up(sizeof(CamDev) * n_cam + sizeof(void*) * n_cam, 256));
+  if (use_graph)
+    FFV_TRY(check(hipMemcpyAsync(view_tab, vd.data(), sizeof(ViewDesc) * n_view_total,
+                                 hipMemcpyHostToDevice, stream_),
+                  "copy view table"));
   Exec xv = x;
   xv.ws = base + fixed;
-  for (int v0 = 0; v0 < n_view_total; v0 += chunk) {
-    const int nv = std::min(chunk, n_view_total - v0);
-    FFV_TRY(run_views(xv, vp, cam_tab, vd.data() + v0, nv));
+  auto launch_all = [&]() -> Status {
+    FFV_TRY(build_cameras(x, g, src_tab, n_cam, blocks.data(), ctmp));
+    for (int v0 = 0; v0 < n_view_total; v0 += chunk) {
+      const int nv = std::min(chunk, n_view_total - v0);
+      FFV_TRY(run_views(xv, vp, cam_tab, use_graph ? view_tab + v0 : vd.data() + v0, nv, use_graph));
+    }
+    return Status::ok();
+  };
+  const GraphEntry* ran = nullptr;
+  if (use_graph) {
+    const GraphKey key{H, W, n_cam, n_view_total, chunk, ws_, vib_fp8(), profiling_};
+    auto it = graph_cache_.find(key);
+    if (it == graph_cache_.end()) {
+      pending_.clear();
+      FFV_TRY(check(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal), "begin capture"));
+      const Status st = launch_all();
+      hipGraph_t graph = nullptr;
+      const hipError_t ec = hipStreamEndCapture(stream_, &graph);
+      GraphEntry entry;
+      entry.prof = std::move(pending_);
+      pending_.clear();
+      if (!st.good() || ec != hipSuccess) {
+        if (graph) hipGraphDestroy(graph);
+        for (auto& pe : entry.prof) {
+          evt_pool_.push_back(pe.a);
+          evt_pool_.push_back(pe.b);
+        }
+        FFV_TRY(st);
+        return check(ec, "end capture");
+      }
+      const hipError_t ei = hipGraphInstantiate(&entry.exec, graph, nullptr, nullptr, 0);
+      hipGraphDestroy(graph);
+      if (ei != hipSuccess) {
+        for (auto& pe : entry.prof) {
+          evt_pool_.push_back(pe.a);
+          evt_pool_.push_back(pe.b);
+        }
+        return check(ei, "graph instantiate");
+      }
+      if (graph_cache_.size() >= 64) {
+        FFV_TRY(check(hipStreamSynchronize(stream_), "hipStreamSynchronize"));
+        drop_graphs();
+      }
+      it = graph_cache_.emplace(key, std::move(entry)).first;
+    }
+    FFV_TRY(check(hipGraphLaunch(it->second.exec, stream_), "graph launch"));
+    ran = &it->second;
+  } else {
+    FFV_TRY(launch_all());
   }
   FFV_TRY(check(hipStreamSynchronize(stream_), "hipStreamSynchronize"));
   last_plan_ = vp;
   last_views_ws_ = xv.ws;
   have_taps_ = true;
   if (profiling_) {
+    if (ran)
+      for (const auto& pe : ran->prof) add_stat(pe);
     for (auto& pe : pending_) {
-      float ms = 0.f;
-      hipEventElapsedTime(&ms, pe.a, pe.b);
-      KernelStat& ks = stats_[pe.cls];
-      ks.launches += 1;
-      ks.ms += ms;
-      ks.work += pe.work;
+      add_stat(pe);
       evt_pool_.push_back(pe.a);
       evt_pool_.push_back(pe.b);
     }
@@ -838,6 +990,233 @@ Status Net::debug_tap(const std::string& name, float* dst, size_t cap, int dims[
   dims[2] = w;
   FFV_TRY(check(launch_extract(src, DType::F32, ld, C, (long)h * w, dst, stream_), "extract"));
   return check(hipStreamSynchronize(stream_), "sync");
+}
+
+// VIBlock layers in execution order; each reads the previous one's output.
+static std::vector<std::string> vib_chain(int s) {
+  std::vector<std::string> v;
+  for (const char* n : {"conv1", "conv2", "conv3", "conv4", "conv5", "conv6", "conv7", "conv8", "convT1",
+                        "convT2"})
+    v.push_back("vib" + std::to_string(s) + "." + n);
+  return v;
+}
+
+Status Net::calibrate(const float* left, const float* right, int H, int W, float t) {
+  if (!fp8_) return Status::err(-7, "calibration applies to FP8 nets");
+  std::lock_guard<std::mutex> lk(call_mu_);
+  FFV_TRY(check(hipSetDevice(device_), "hipSetDevice"));
+  for (int s = 0; s < 3; ++s)
+    for (const std::string& nm : vib_chain(s)) {
+      Layer& L = layers_.at(nm);
+      if (!L.amax) FFV_TRY(check(hipMalloc((void**)&L.amax, sizeof(float) * L.cout), "hipMalloc amax"));
+      FFV_TRY(check(hipMemsetAsync(L.amax, 0, sizeof(float) * L.cout, stream_), "zero amax"));
+    }
+  float* out = nullptr;
+  FFV_TRY(check(hipMalloc((void**)&out, sizeof(float) * 3 * (size_t)H * W), "hipMalloc"));
+  calibrating_ = true;
+  Status st = interpolate_locked(&left, &right, 1, H, W, &t, 1, out);
+  calibrating_ = false;
+  hipFree(out);
+  FFV_TRY(st);
+  for (int s = 0; s < 3; ++s)
+    for (const std::string& nm : vib_chain(s)) {
+      Layer& L = layers_.at(nm);
+      std::vector<float> amax(L.cout);
+      FFV_TRY(check(hipMemcpy(amax.data(), L.amax, sizeof(float) * L.cout, hipMemcpyDeviceToHost),
+                    "read amax"));
+      L.act_scale.resize(L.cout);
+      for (int o = 0; o < L.cout; ++o) L.act_scale[o] = std::max(amax[o], 1e-6f) / 448.f;
+    }
+  FFV_TRY(quantize_vib_layers());
+  calibrated_ = true;
+  return Status::ok();
+}
+
+// Quantise the VIBlock layers that read fp8 activations: the producer's
+// per-channel activation scale is folded into the weights, then each output
+// channel gets its own weight scale (max |w'| / 448). Producers get their
+// output quantisation scale 1 / activation scale.
+Status Net::quantize_vib_layers() {
+  for (int s = 0; s < 3; ++s) {
+    const std::vector<std::string> chain = vib_chain(s);
+    for (size_t li = 0; li < chain.size(); ++li) {
+      Layer& L = layers_.at(chain[li]);
+      if (li + 1 < chain.size()) {
+        std::vector<float> inv(L.cout);
+        for (int o = 0; o < L.cout; ++o) inv[o] = 1.f / L.act_scale[o];
+        if (!L.out_scale)
+          FFV_TRY(check(hipMalloc((void**)&L.out_scale, sizeof(float) * L.cout), "hipMalloc scale"));
+        FFV_TRY(check(hipMemcpy(L.out_scale, inv.data(), sizeof(float) * L.cout, hipMemcpyHostToDevice),
+                      "copy scale"));
+      }
+      if (li == 0) continue;  // conv1 reads the bf16 stage input
+      const Layer& P = layers_.at(chain[li - 1]);
+      std::vector<float> w = L.w_host;
+      const int taps = L.transposed ? 16 : 9;
+      // fold the input channel scale: conv [o][c][t], transposed [c][o][t]
+      for (int c = 0; c < L.cin; ++c)
+        for (int o = 0; o < L.cout; ++o)
+          for (int k = 0; k < taps; ++k) {
+            const size_t idx = L.transposed ? ((size_t)c * L.cout + o) * taps + k
+                                            : ((size_t)o * L.cin + c) * taps + k;
+            w[idx] *= P.act_scale[c];
+          }
+      std::vector<float> ws(L.cout, 0.f);
+      for (int c = 0; c < L.cin; ++c)
+        for (int o = 0; o < L.cout; ++o)
+          for (int k = 0; k < taps; ++k) {
+            const size_t idx = L.transposed ? ((size_t)c * L.cout + o) * taps + k
+                                            : ((size_t)o * L.cin + c) * taps + k;
+            ws[o] = std::max(ws[o], std::fabs(w[idx]));
+          }
+      for (int o = 0; o < L.cout; ++o) ws[o] = std::max(ws[o], 1e-30f) / 448.f;
+      for (int c = 0; c < L.cin; ++c)
+        for (int o = 0; o < L.cout; ++o)
+          for (int k = 0; k < taps; ++k) {
+            const size_t idx = L.transposed ? ((size_t)c * L.cout + o) * taps + k
+                                            : ((size_t)o * L.cin + c) * taps + k;
+            w[idx] /= ws[o];
+          }
+      const int k_pad = round_up(L.K, 128);
+      std::vector<float> pf = pack_layer_f(L, conv_k_step(DType::FP8), k_pad, w);
+      std::vector<uint8_t> q(pf.size());
+      for (size_t i = 0; i < pf.size(); ++i) q[i] = f2f8(pf[i]);
+      if (!L.w8_dev) FFV_TRY(check(hipMalloc(&L.w8_dev, q.size()), "hipMalloc fp8 weights"));
+      FFV_TRY(check(hipMemcpy(L.w8_dev, q.data(), q.size(), hipMemcpyHostToDevice), "copy fp8 weights"));
+      if (!L.w8_scale)
+        FFV_TRY(check(hipMalloc((void**)&L.w8_scale, sizeof(float) * L.cout), "hipMalloc w scale"));
+      FFV_TRY(check(hipMemcpy(L.w8_scale, ws.data(), sizeof(float) * L.cout, hipMemcpyHostToDevice),
+                    "copy w scale"));
+    }
+  }
+  return Status::ok();
+}
+
+Status Net::autotune(const float* const* left, const float* const* right, int n_pairs, int H, int W,
+                     const float* t, int n_t, float* out, int* n_tuned) {
+  if (n_tuned) *n_tuned = 0;
+  // 1. run the call once, recording every conv launch (eager, so each
+  //    launch passes through conv()); its output is the call's result
+  std::lock_guard<std::mutex> lk(call_mu_);
+  recs_.clear();
+  recording_ = true;
+  Status st = interpolate_locked(left, right, n_pairs, H, W, t, n_t, out);
+  recording_ = false;
+  FFV_TRY(st);
+  // 2. re-run each recorded launch with every candidate tile shape. The
+  //    launches read and write only the workspace, whose contents are dead
+  //    once the call has returned, and conv kernels address memory from
+  //    their shapes alone, whatever values they meet.
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  FFV_TRY(check(hipEventCreate(&e0), "hipEventCreate"));
+  Status res = check(hipEventCreate(&e1), "hipEventCreate");
+  std::map<TuneKey, TuneVal> found;
+  const ConvTile tiles[4] = {ConvTile::N256, ConvTile::N128, ConvTile::N64, ConvTile::N32};
+  const int widths[4] = {8, 16, 32, 64};
+  for (size_t r = 0; res.good() && r < recs_.size(); ++r) {
+    const TuneRec& rec = recs_[r];
+    if (found.count(rec.key)) continue;
+    const int rows32 = round_up(rec.a.n_rows, 32);
+    long min_area = -1;
+    for (int tw : widths) {
+      const int th = 256 / tw;
+      const long area = (long)((rec.a.Ho + th - 1) / th) * th * ((rec.a.Wo + tw - 1) / tw) * tw;
+      if (min_area < 0 || area < min_area) min_area = area;
+    }
+    float best_ms = -1.f;
+    TuneVal best{};
+    for (int ti = 0; res.good() && ti < 4; ++ti) {
+      const int bn = 256 >> ti;
+      if (bn >= 2 * rows32) continue;  // at least half of every tile's columns real
+      for (int tw : widths) {
+        const int th = 256 / tw;
+        const long area = (long)((rec.a.Ho + th - 1) / th) * th * ((rec.a.Wo + tw - 1) / tw) * tw;
+        if (area * 10 > min_area * 11) continue;  // within 10 % of the least padding
+        ConvArgs a = rec.a;
+        a.tile_w = tw;
+        a.amax = nullptr;
+        res = check(launch_conv(rec.dt, tiles[ti], a, stream_), "autotune warm-up");
+        if (!res.good()) break;
+        res = check(hipEventRecord(e0, stream_), "hipEventRecord");
+        const int reps = 2;
+        for (int k = 0; res.good() && k < reps; ++k)
+          res = check(launch_conv(rec.dt, tiles[ti], a, stream_), "autotune launch");
+        if (res.good()) res = check(hipEventRecord(e1, stream_), "hipEventRecord");
+        if (res.good()) res = check(hipEventSynchronize(e1), "hipEventSynchronize");
+        float ms = 0.f;
+        if (res.good()) res = check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        if (!res.good()) break;
+        ms /= reps;
+        if (best_ms < 0.f || ms < best_ms) {
+          best_ms = ms;
+          best = TuneVal{tiles[ti], tw};
+        }
+      }
+    }
+    if (res.good() && best_ms >= 0.f) found[rec.key] = best;
+  }
+  hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  recs_.clear();
+  FFV_TRY(res);
+  for (auto& kv : found) tuned_[kv.first] = kv.second;
+  FFV_TRY(check(hipStreamSynchronize(stream_), "hipStreamSynchronize"));
+  drop_graphs();  // captured with the previous tile choices
+  if (n_tuned) *n_tuned = (int)found.size();
+  return Status::ok();
+}
+
+static int tile_bn(ConvTile t) { return 256 >> (int)t; }
+
+Status Net::save_tuning(const std::string& path) {
+  std::lock_guard<std::mutex> lk(call_mu_);
+  FILE* f = std::fopen(path.c_str(), "w");
+  if (!f) return Status::err(-1, "cannot open " + path + " for writing");
+  std::fprintf(f, "# ffv conv tuning v1: layer fp8 Ho Wo n_img n_tile tile_w\n");
+  for (auto& kv : tuned_)
+    std::fprintf(f, "%s %d %d %d %d %d %d\n", kv.first.layer.c_str(), kv.first.fp8, kv.first.Ho,
+                 kv.first.Wo, kv.first.n_img, tile_bn(kv.second.tile), kv.second.tile_w);
+  const bool ok = std::fclose(f) == 0;
+  return ok ? Status::ok() : Status::err(-1, "write failed: " + path);
+}
+
+Status Net::load_tuning(const std::string& path, int* n_loaded) {
+  std::lock_guard<std::mutex> lk(call_mu_);
+  if (n_loaded) *n_loaded = 0;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return Status::err(-1, "cannot open " + path);
+  std::map<TuneKey, TuneVal> got;
+  char line[512];
+  int lineno = 0;
+  Status st = Status::ok();
+  while (std::fgets(line, sizeof line, f)) {
+    ++lineno;
+    if (line[0] == '#' || line[0] == '\n') continue;
+    char name[256];
+    int fp8, ho, wo, n, bn, tw;
+    if (std::sscanf(line, "%255s %d %d %d %d %d %d", name, &fp8, &ho, &wo, &n, &bn, &tw) != 7 ||
+        (fp8 != 0 && fp8 != 1) || ho <= 0 || wo <= 0 || n <= 0 ||
+        (bn != 256 && bn != 128 && bn != 64 && bn != 32) || tw <= 0 || tw > 256 || 256 % tw != 0 ||
+        !layers_.count(name)) {
+      st = Status::err(-1, path + ": bad entry on line " + std::to_string(lineno));
+      break;
+    }
+    const Layer& L = layers_.at(name);
+    if (L.name == "unet.head" || bn > L.cout_pad) {
+      st = Status::err(-1, path + ": entry on line " + std::to_string(lineno) + " does not fit its layer");
+      break;
+    }
+    const ConvTile t = bn == 256 ? ConvTile::N256
+                                 : (bn == 128 ? ConvTile::N128 : (bn == 64 ? ConvTile::N64 : ConvTile::N32));
+    got[TuneKey{name, fp8, ho, wo, n}] = TuneVal{t, tw};
+  }
+  std::fclose(f);
+  FFV_TRY(st);
+  for (auto& kv : got) tuned_[kv.first] = kv.second;
+  if (stream_) hipStreamSynchronize(stream_);
+  drop_graphs();
+  if (n_loaded) *n_loaded = (int)got.size();
+  return Status::ok();
 }
 
 Status Net::start_serving(size_t budget, float tick_ms, int max_batch_views) {

@@ -7,6 +7,7 @@
 #include <condition_variable>
 #include <deque>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -37,11 +38,20 @@ struct Layer {
   int cin = 0, cout = 0, stride = 1;
   int cin_pad = 0, K = 0, K_pad = 0, cout_pad = 0;
   int mode = 0;  // ConvArgs::transposed: 0 conv, 1 per-phase transposed, 2 phase-merged
-  ConvTile tile = ConvTile::N256;
+  int rows = 0;  // GEMM N: cout, or 4 * cout phase-merged
+  ConvTile tile = ConvTile::N256;  // default N tile (narrowest that covers rows)
   std::vector<float> w_host;  // file layout
   std::vector<float> b_host;
   void* w_dev = nullptr;      // packed [phase][cout_pad][K_pad], activation dtype
   float* b_dev = nullptr;
+  // FP8 (VIBlock 128/256-channel layers): fp8 weights with the producer's
+  // activation scales folded in, the per-output-channel dequant scale, the
+  // output quantisation scale (1 / activation scale) and calibration amax.
+  void* w8_dev = nullptr;
+  float* w8_scale = nullptr;
+  float* out_scale = nullptr;
+  float* amax = nullptr;
+  std::vector<float> act_scale;  // per output channel: |activation| max / 448
 };
 
 struct WeightsFile {
@@ -108,9 +118,23 @@ class Net {
   Status interpolate(const float* const* left, const float* const* right, int n_pairs, int H, int W,
                      const float* t, int n_t, float* out);
   Status debug_tap(const std::string& name, float* dst, size_t cap, int dims[3]);
+  // FP8 nets: run one view in bf16, record the VIBlock activations' per-channel
+  // ranges, then quantise those layers' weights (needed before use).
+  Status calibrate(const float* left, const float* right, int H, int W, float t);
+  bool ready() const { return !fp8_ || calibrated_; }
   void set_debug(bool on) { debug_ = on; }
+  // Replay interpolate()'s launch sequence as one hipGraph per call shape.
+  void set_graphs(bool on);
   void set_profiling(bool on);
   Status kernel_stats(const std::string& name, long* launches, double* ms, double* work);
+  // Runs the call like interpolate(), then times every candidate tile shape
+  // (N tile width, M-tile pixel block width) of each convolution launch of
+  // that call and keeps the fastest for its (layer, precision, grid,
+  // images); later calls of that shape use them. *n_tuned = launches tuned.
+  Status autotune(const float* const* left, const float* const* right, int n_pairs, int H, int W,
+                  const float* t, int n_t, float* out, int* n_tuned);
+  Status save_tuning(const std::string& path);
+  Status load_tuning(const std::string& path, int* n_loaded);
   DType dtype() const { return dt_; }
   int device() const { return device_; }
   hipStream_t stream() const { return stream_; }
@@ -127,17 +151,24 @@ class Net {
   // array of device pointers). ctmp is scratch of n_cam * cp.ctmp bytes.
   Status build_cameras(const Exec& x, const Geo& g, const float* const* src_dev, int n_cam,
                        char* const* blocks, char* ctmp);
-  // Run nv views (descriptors on the host, copied to the plan's view slot).
-  Status run_views(const Exec& x, const ViewPlan& p, const CamDev* cams_dev,
-                   const ViewDesc* views_host, int nv);
+  // Run nv views. views_on_device: `views` is a device table that stays
+  // valid until the work completes; otherwise a host array copied to the
+  // plan's view slot on the stream.
+  Status run_views(const Exec& x, const ViewPlan& p, const CamDev* cams_dev, const ViewDesc* views,
+                   int nv, bool views_on_device = false);
   CamDev cam_dev(const Geo& g, char* block) const;
   Status check(hipError_t e, const char* what) const;
 
  private:
+  Status interpolate_locked(const float* const* left, const float* const* right, int n_pairs, int H,
+                            int W, const float* t, int n_t, float* out);
   Status ensure_workspace(size_t bytes);
+  void drop_graphs();
   Status conv(const Exec& x, const Layer& L, const void* in, int in_ld, long in_img_stride, int Hi,
               int Wi, int n_img, void* out, int out_ld, long out_img_stride, bool out_f32,
-              bool accumulate, bool relu);
+              bool accumulate, bool relu, bool in_fp8 = false, bool out_fp8 = false);
+  bool vib_fp8() const { return fp8_ && calibrated_ && !calibrating_; }
+  Status quantize_vib_layers();
   const Layer& layer(const std::string& n) const { return layers_.at(n); }
   void prof_begin(const Exec& x);
   void prof_end(const Exec& x, const char* cls, double work);
@@ -146,6 +177,9 @@ class Net {
   int base_width_ = 32;
   bool t_plane_ = true;
   DType dt_ = DType::F32;
+  bool fp8_ = false;          // FP8 VIBlocks (activation dtype elsewhere: bf16)
+  bool calibrated_ = false;
+  bool calibrating_ = false;
   int device_ = 0;
   hipStream_t stream_ = nullptr;
   bool own_stream_ = false;
@@ -159,12 +193,56 @@ class Net {
   char* last_views_ws_ = nullptr;
   std::mutex call_mu_;        // serialises interpolate() per net
 
-  bool profiling_ = false;
+  // A timed kernel class interval: events recorded before and after.
   struct PendingEvt {
     hipEvent_t a, b;
     std::string cls;
     double work;
   };
+  // Instantiated graphs of interpolate(), by call shape. Every pointer the
+  // kernels take is either the net's (weights, workspace) or read from the
+  // device tables written before each replay, so a graph depends only on
+  // the key. With profiling on, the graph holds event-record nodes around
+  // each kernel class (its `prof` intervals, read after every replay).
+  struct GraphKey {
+    int H, W, n_cam, n_view, chunk;
+    const void* ws;
+    bool fp8, prof;
+    bool operator<(const GraphKey& o) const {
+      return std::tie(H, W, n_cam, n_view, chunk, ws, fp8, prof) <
+             std::tie(o.H, o.W, o.n_cam, o.n_view, o.chunk, o.ws, o.fp8, o.prof);
+    }
+  };
+  struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    std::vector<PendingEvt> prof;
+  };
+  bool graphs_ = true;
+  std::map<GraphKey, GraphEntry> graph_cache_;
+  void add_stat(const PendingEvt& pe);
+
+  // Tile choices found by autotune(), per conv launch shape.
+  struct TuneKey {
+    std::string layer;
+    int fp8, Ho, Wo, n_img;
+    bool operator<(const TuneKey& o) const {
+      return std::tie(layer, fp8, Ho, Wo, n_img) < std::tie(o.layer, o.fp8, o.Ho, o.Wo, o.n_img);
+    }
+  };
+  struct TuneVal {
+    ConvTile tile;
+    int tile_w;
+  };
+  std::map<TuneKey, TuneVal> tuned_;
+  bool recording_ = false;  // conv() records its launches for autotune()
+  struct TuneRec {
+    TuneKey key;
+    ConvArgs a;
+    DType dt;
+  };
+  std::vector<TuneRec> recs_;
+
+  bool profiling_ = false;
   std::vector<PendingEvt> pending_;
   std::vector<hipEvent_t> evt_pool_;
   hipEvent_t cur_start_ = nullptr;

@@ -130,6 +130,7 @@ Status Server::register_camera(int cam_id, const float* image, int H, int W) {
 
 Status Server::submit(const Request& r, uint64_t* ticket) {
   if (!r.out) return Status::err(-1, "null output pointer");
+  if (!net_->ready()) return Status::err(-7, "FP8 net needs ffv_calibrate first");
   if (!(r.t >= 0.f && r.t <= 1.f)) return Status::err(-1, "t must lie in [0, 1]");
   std::lock_guard<std::mutex> lk(mu_);
   auto a = cams_.find(r.cam_l), b = cams_.find(r.cam_r);

@@ -25,8 +25,9 @@ STATUS = {0: "FFV_OK", 1: "FFV_PENDING", -1: "FFV_ERR_ARG", -2: "FFV_ERR_OOM",
 
 # Every symbol include/ffv.h declares.
 EXPORTS = ["ffv_default_opts", "ffv_create_net", "ffv_destroy_net", "ffv_interpolate",
-           "ffv_last_error", "ffv_register_camera", "ffv_submit", "ffv_poll", "ffv_serving_stats",
-           "ffv_debug_tap", "ffv_set_debug", "ffv_set_profiling", "ffv_kernel_stats", "ffv_op_conv"]
+           "ffv_last_error", "ffv_calibrate", "ffv_register_camera", "ffv_submit", "ffv_poll", "ffv_serving_stats",
+           "ffv_debug_tap", "ffv_set_debug", "ffv_set_profiling", "ffv_kernel_stats", "ffv_op_conv",
+           "ffv_autotune", "ffv_save_tuning", "ffv_load_tuning"]
 
 
 class FfvError(RuntimeError):
@@ -37,7 +38,7 @@ class FfvError(RuntimeError):
 
 class ffv_opts(ctypes.Structure):
     _fields_ = [("abi_version", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("graphs", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
                 ("hbm_budget_bytes", ctypes.c_uint64), ("tick_ms", ctypes.c_float),
                 ("max_batch_views", ctypes.c_int32)]
@@ -91,8 +92,17 @@ def lib() -> ctypes.CDLL:
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     L.ffv_kernel_stats.restype = c_int
     L.ffv_op_conv.argtypes = [c_int, c_void, c_int, c_int, c_int, c_int, c_void, c_void, c_int,
-                              c_int, c_int, c_int, c_void, c_void]
+                              c_int, c_int, c_int, c_int, c_int, c_void, c_void]
     L.ffv_op_conv.restype = c_int
+    L.ffv_autotune.argtypes = [c_void, ctypes.POINTER(ffv_pair), c_int, ctypes.POINTER(c_f), c_int,
+                               c_void, ctypes.POINTER(c_int)]
+    L.ffv_autotune.restype = c_int
+    L.ffv_save_tuning.argtypes = [c_void, ctypes.c_char_p]
+    L.ffv_save_tuning.restype = c_int
+    L.ffv_load_tuning.argtypes = [c_void, ctypes.c_char_p, ctypes.POINTER(c_int)]
+    L.ffv_load_tuning.restype = c_int
+    L.ffv_calibrate.argtypes = [c_void, ctypes.POINTER(ffv_pair), c_f]
+    L.ffv_calibrate.restype = c_int
     L.ffv_register_camera.argtypes = [c_void, c_int, c_void, c_int, c_int]
     L.ffv_register_camera.restype = c_int
     L.ffv_submit.argtypes = [c_void, ctypes.POINTER(ffv_request), ctypes.POINTER(ctypes.c_uint64)]
@@ -127,7 +137,7 @@ class Net:
 
     def __init__(self, weights_path: str, precision: str = "fp32", device: int = 0,
                  workspace_bytes: int = 0, hbm_budget_bytes: int = 0, tick_ms: float = 5.0,
-                 max_batch_views: int = 0):
+                 max_batch_views: int = 0, graphs: bool = True):
         L = lib()
         self.device = torch.device("cuda", device)
         # The library works on this stream; calls order it after the caller's
@@ -142,6 +152,7 @@ class Net:
         opts.hbm_budget_bytes = hbm_budget_bytes
         opts.tick_ms = tick_ms
         opts.max_batch_views = max_batch_views
+        opts.graphs = 1 if graphs else 0
         h = ctypes.c_void_p()
         _check(L.ffv_create_net(os.fsencode(weights_path), ctypes.byref(opts), ctypes.byref(h)))
         self._h = h
@@ -161,6 +172,28 @@ class Net:
     def interpolate(self, pairs, ts, out: torch.Tensor | None = None) -> torch.Tensor:
         """``pairs``: list of (left, right) [3, H, W] float32 CUDA tensors.
         ``ts``: phases in [0, 1]. Returns [n_pairs, n_t, 3, H, W] float32."""
+        arr, tarr, out = self._call_args(pairs, ts, out)
+        _check(lib().ffv_interpolate(self._h, arr, len(arr), tarr, len(tarr), out.data_ptr()))
+        return out
+
+    def autotune(self, pairs, ts, out: torch.Tensor | None = None) -> int:
+        """Run the call as ``interpolate`` does, then tune the conv tiles of
+        its launches; returns the number of launch shapes tuned."""
+        arr, tarr, out = self._call_args(pairs, ts, out)
+        n = ctypes.c_int32(0)
+        _check(lib().ffv_autotune(self._h, arr, len(arr), tarr, len(tarr), out.data_ptr(),
+                                  ctypes.byref(n)))
+        return n.value
+
+    def save_tuning(self, path: str):
+        _check(lib().ffv_save_tuning(self._h, os.fsencode(path)))
+
+    def load_tuning(self, path: str) -> int:
+        n = ctypes.c_int32(0)
+        _check(lib().ffv_load_tuning(self._h, os.fsencode(path), ctypes.byref(n)))
+        return n.value
+
+    def _call_args(self, pairs, ts, out):
         pairs = list(pairs)
         ts = [float(t) for t in ts]
         if not pairs or not ts:
@@ -181,8 +214,15 @@ class Net:
             raise ValueError("out has the wrong size")
         tarr = (ctypes.c_float * len(ts))(*ts)
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
-        _check(lib().ffv_interpolate(self._h, arr, len(pairs), tarr, len(ts), out.data_ptr()))
-        return out
+        return arr, tarr, out
+
+    def calibrate(self, left: torch.Tensor, right: torch.Tensor, t: float = 0.5):
+        """FP8 nets: set the activation scales from one representative view."""
+        _dev_f32(left, "left")
+        _dev_f32(right, "right")
+        pr = ffv_pair(left.data_ptr(), right.data_ptr(), int(left.shape[1]), int(left.shape[2]))
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        _check(lib().ffv_calibrate(self._h, ctypes.byref(pr), float(t)))
 
     # ---------------------------------------------------------------- serving
     def register_camera(self, cam_id: int, image: torch.Tensor):
@@ -247,10 +287,12 @@ class Net:
 
 
 def op_conv(x: torch.Tensor, weight, bias, stride: int = 1, transposed: bool = False,
-            relu: bool = False, precision: str = "fp32") -> torch.Tensor:
+            relu: bool = False, precision: str = "fp32", n_tile: int = 0,
+            tile_w: int = 0) -> torch.Tensor:
     """One conv layer through the library's implicit-GEMM kernel.
     ``x``: [n, cin, h, w] float32 CUDA; ``weight``/``bias``: host arrays in
-    the weights-file layout."""
+    the weights-file layout; ``n_tile``/``tile_w``: kernel variant (0 =
+    default)."""
     import numpy as np
     _dev_f32(x, "x")
     n, cin, h, w = x.shape
@@ -265,5 +307,5 @@ def op_conv(x: torch.Tensor, weight, bias, stride: int = 1, transposed: bool = F
     s = torch.cuda.current_stream(x.device)
     _check(lib().ffv_op_conv(PRECISIONS[precision], x.data_ptr(), n, cin, h, w,
                              wt.ctypes.data, bs.ctypes.data, cout, stride, 1 if transposed else 0,
-                             1 if relu else 0, y.data_ptr(), s.cuda_stream))
+                             1 if relu else 0, n_tile, tile_w, y.data_ptr(), s.cuda_stream))
     return y

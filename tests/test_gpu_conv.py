@@ -69,3 +69,45 @@ def test_conv_kernel_vs_oracle(cin, cout, h, w, stride, transposed, precision):
     # of |terms|
     bound = 2e-5 * absref + 1e-6
     assert np.all(err <= bound), (err.max(), (err / (absref + 1e-12)).max())
+
+
+VARIANT_CASES = [
+    # (cin, cout, h, w, stride, transposed): shapes that span several M tiles
+    (64, 256, 40, 52, 1, False),
+    (128, 128, 37, 45, 2, False),
+    (256, 128, 19, 23, 0, True),
+    (64, 16, 21, 27, 0, True),
+]
+
+
+@pytest.mark.parametrize("cin,cout,h,w,stride,transposed", VARIANT_CASES)
+def test_conv_tile_variants_agree(cin, cout, h, w, stride, transposed):
+    """Every (N tile, pixel-block width) the autotuner may choose computes
+    the same output: each element is one fp32 MFMA chain over the same K
+    order, whatever the tiling, so the results agree bit for bit and match
+    the oracle."""
+    from paper_2112_10603_amd import op_conv
+    print(f"case tile variants cin={cin} cout={cout} h={h} w={w} s={stride} T={transposed}", flush=True)
+    rng = np.random.default_rng(cin + 7 * cout)
+    x = rng.standard_normal((2, cin, h, w)).astype(np.float32)
+    if transposed:
+        wt = (rng.standard_normal((cin, cout, 4, 4)) / np.sqrt(4 * cin)).astype(np.float32)
+    else:
+        wt = (rng.standard_normal((cout, cin, 3, 3)) / np.sqrt(9 * cin)).astype(np.float32)
+    b = rng.standard_normal(cout).astype(np.float32)
+    xd = torch.from_numpy(x).cuda()
+    base = op_conv(xd, wt, b, stride=max(stride, 1), transposed=transposed, relu=True,
+                   precision="bf16").cpu()
+    xr = torch.from_numpy(x).bfloat16().double().numpy()
+    wr = torch.from_numpy(wt).bfloat16().double().numpy()
+    ref = _ref(xr, wr, b.astype(np.float64), stride, transposed, True)
+    absref = _ref(np.abs(xr), np.abs(wr), np.abs(b).astype(np.float64), stride, transposed, False)
+    assert np.all(np.abs(base.numpy() - ref) <= 2e-5 * absref + 1e-6)
+    rows = 4 * cout if (transposed and cout <= 16) else cout
+    for n_tile in (256, 128, 64, 32):
+        if n_tile >= 2 * ((rows + 31) // 32 * 32):
+            continue
+        for tile_w in (8, 16, 32, 64):
+            got = op_conv(xd, wt, b, stride=max(stride, 1), transposed=transposed, relu=True,
+                          precision="bf16", n_tile=n_tile, tile_w=tile_w).cpu()
+            assert torch.equal(got, base), (n_tile, tile_w, (got - base).abs().max().item())

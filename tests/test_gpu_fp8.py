@@ -1,0 +1,88 @@
+"""FP8 nets (VIBlock 128/256-channel convs in fp8 e4m3 with per-channel
+scales, calibrated by the library on one view): closed forms still exact,
+batch invariance, and the error against the FP64 oracle reported."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import vinet as O
+from synth import scenes
+from synth.weights import write_weights_file
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def psnr(a, b):
+    mse = float(np.mean((np.asarray(a, np.float64) - np.asarray(b, np.float64)) ** 2))
+    return float("inf") if mse == 0 else 10 * math.log10(1.0 / mse)
+
+
+@pytest.fixture(scope="module")
+def wfile(tmp_path_factory):
+    return write_weights_file(str(tmp_path_factory.mktemp("w8") / "w0.ffvw"), seed=0)
+
+
+def _fp8_net(path, calib):
+    from paper_2112_10603_amd import Net
+    net = Net(path, "fp8", 0)
+    net.calibrate(calib[0].to(DEV), calib[1].to(DEV), 0.5)
+    return net
+
+
+def test_fp8_needs_calibration(wfile):
+    from paper_2112_10603_amd import FfvError, Net
+    net = Net(wfile, "fp8", 0)
+    x = torch.rand(3, 32, 32, device=DEV)
+    with pytest.raises(FfvError) as e:
+        net.interpolate([(x, x)], [0.5])
+    assert e.value.code == -7
+    net.close()
+
+
+def test_fp8_zero_heads_exact(tmp_path):
+    print("case fp8 zero heads", flush=True)
+    p = write_weights_file(str(tmp_path / "z.ffvw"), seed=3, kind="zero_heads")
+    calib = scenes.random_pair(99, 64, 64)
+    net = _fp8_net(p, calib)
+    xl, xr = scenes.random_pair(7, 40, 72)
+    out = net.interpolate([(xl.to(DEV), xr.to(DEV))], [0.3])[0, 0].cpu().numpy()
+    want = 0.5 * (xl.numpy().astype(np.float64) + xr.numpy().astype(np.float64))
+    assert np.abs(out - want).max() <= 1e-6
+    net.close()
+
+
+def test_fp8_batch_invariance(wfile):
+    print("case fp8 batch invariance", flush=True)
+    calib = scenes.random_pair(99, 96, 96)
+    net = _fp8_net(wfile, calib)
+    arc = scenes.camera_arc(31, 64, 96, 3, 96, (3.0, 10.0), 6.0, 0.01).to(DEV)
+    pairs = [(arc[0], arc[1]), (arc[1], arc[2])]
+    ts = [0.2, 0.7]
+    batch = net.interpolate(pairs, ts).cpu()
+    for i in range(2):
+        for j, t in enumerate(ts):
+            alone = net.interpolate([pairs[i]], [t])[0, 0].cpu()
+            assert torch.equal(alone, batch[i, j])
+    net.close()
+
+
+def test_fp8_error_vs_oracle(wfile):
+    """Report FP8 PSNR against the FP64 oracle on a 256x256 crop of the
+    1080p arc (calibrated on a different seeded scene); the bound is loose:
+    fp8 e4m3 carries 3 mantissa bits."""
+    print("case fp8 psnr", flush=True)
+    arc = scenes.hd_arc(2)
+    xl = arc[0, :, 300:556, 800:1056].contiguous()
+    xr = arc[1, :, 300:556, 800:1056].contiguous()
+    cal = scenes.hd_arc(2, seed=99)
+    net = _fp8_net(wfile, (cal[0, :, 0:256, 0:256].contiguous(), cal[1, :, 0:256, 0:256].contiguous()))
+    out = net.interpolate([(xl.to(DEV), xr.to(DEV))], [0.5])[0, 0].cpu().numpy()
+    ref = O.vinet_forward(xl.numpy(), xr.numpy(), 0.5, O.load_weights(wfile))
+    p = psnr(out, ref)
+    print(f"  FP8 PSNR vs oracle {p:.2f} dB, max-abs {np.abs(out - ref).max():.3e}")
+    assert p >= 25.0
+    net.close()
