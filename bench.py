@@ -35,6 +35,47 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
 
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "conv_igemm_dense1080p_bf16_hbm_counters.md")
+CONV_SOURCES = [os.path.join(ROOT, "paper_2112_10603_amd", "csrc", f) for f in ("conv_kernel.h", "conv.hip")]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the 256->256 conv class from the committed
+    counter summary (two rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE,
+    scaled by a plain copy), or None when the conv kernel sources no longer
+    hash to the value the counters were taken with."""
+    import hashlib
+    import re
+    try:
+        text = open(COUNTERS_FILE).read()
+    except OSError:
+        return None
+    h = re.search(r"kernel-source-sha256: ([0-9a-f]{64})", text)
+    t = re.search(r"conv256-traffic-bytes-per-launch: (\d+)", text)
+    if not h or not t:
+        return None
+    cur = hashlib.sha256()
+    for f in CONV_SOURCES:
+        cur.update(open(f, "rb").read())
+    return int(t.group(1)) if cur.hexdigest() == h.group(1) else None
+
+
+def conv256_ideal_bytes(n_views, Hp, Wp, width=256):
+    """Algorithmic HBM bytes per launch of the 256->256 conv class, averaged
+    over its launches in one step: each launch reads its BF16 input once,
+    writes its BF16 output once and reads its weights once. The class is the
+    six 3x3 256->256 convs of each VIBlock (at 1/16, 1/8, 1/4 of the padded
+    pixels) and the deepest U-Net encoder conv (1/16)."""
+    w_bytes = width * width * 9 * 2
+    sizes = []
+    for s in range(3):
+        px = (Hp * (1 << s) // 16) * (Wp * (1 << s) // 16)
+        sizes += [px] * 6
+    sizes.append((Hp // 16) * (Wp // 16))
+    per = [2 * n_views * px * width * 2 + w_bytes for px in sizes]
+    return sum(per) / len(per)
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -189,6 +230,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 4K leg")
     ap.add_argument("--no-tune", action="store_true", help="skip conv tile autotuning")
+    ap.add_argument("--tune-file", default=None,
+                    help="load the conv tuning table from this file if it exists, else tune and "
+                         "save it there")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -226,12 +270,17 @@ def main():
     net = Net(wpath, "bf16", 0, workspace_bytes=128 << 30)
     out = torch.empty((len(pairs), len(ts), 3, H, W), dtype=torch.float32, device=dev)
     tune = None
-    if not args.no_tune:
+    if args.tune_file and os.path.exists(args.tune_file):
+        tune = {"launch_shapes": net.load_tuning(args.tune_file), "loaded_from": args.tune_file}
+        print(f"[bench] loaded {tune['launch_shapes']} conv tile choices", file=sys.stderr, flush=True)
+    elif not args.no_tune:
         a = time.perf_counter()
         n_tuned = net.autotune(pairs, ts, out)
         tune = {"launch_shapes": n_tuned, "seconds": round(time.perf_counter() - a, 2)}
         print(f"[bench] autotuned {n_tuned} conv launch shapes in {tune['seconds']} s",
               file=sys.stderr, flush=True)
+        if args.tune_file:
+            net.save_tuning(args.tune_file)
     # profiling on before the warm-up, so the warm-up captures the graph the
     # timed steps replay; switching it on again clears the warm-up's stats
     net.set_profiling(True)
@@ -264,8 +313,13 @@ def main():
         avg_ms = dom["ms"] / dom["launches"]
         flops_per_launch = dom["work"] / dom["launches"]
         achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+        default_workload = (H, W, args.cams, args.phases) == (1080, 1920, 8, 16)
+        traffic = measured_traffic() if default_workload else None
+        Hp, Wp = (H + 15) // 16 * 16, (W + 15) // 16 * 16
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                "algorithmic_bytes_per_launch": round(conv256_ideal_bytes(n_views, Hp, Wp)),
                 "kernel": "conv_igemm bf16, 3x3 256->256 (VIBlock conv3-8)",
                 "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": flops_per_launch}
     conv_ms = sum(stats[k]["ms"] for k in ("conv256", "conv", "convT"))

@@ -8,6 +8,7 @@
 // work the library does does not depend on the pixel values.
 //
 // usage: ffv_drive WEIGHTS [precision=1] [H=1080] [W=1920] [n_cams=8] [n_t=16] [reps=1]
+//                  [tuning_file]
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -50,7 +51,8 @@ __global__ void make_view(float* img, int H, int W, int j) {
 
 int main(int argc, char** argv) {
   if (argc < 2) {
-    std::fprintf(stderr, "usage: %s WEIGHTS [precision] [H] [W] [n_cams] [n_t] [reps]\n", argv[0]);
+    std::fprintf(stderr, "usage: %s WEIGHTS [precision] [H] [W] [n_cams] [n_t] [reps] [tuning]\n",
+                 argv[0]);
     return 2;
   }
   const int precision = argc > 2 ? std::atoi(argv[2]) : 1;
@@ -87,10 +89,20 @@ int main(int argc, char** argv) {
   ffv_default_opts(&o);
   o.precision = precision;
   o.workspace_bytes = 128ULL << 30;
+  o.graphs = 0;  // eager launches: hardware counters are read per dispatch
   ffv_net* net = nullptr;
   if (ffv_create_net(argv[1], &o, &net) != FFV_OK) {
     std::fprintf(stderr, "ffv_create_net: %s\n", ffv_last_error());
     return 1;
+  }
+  if (argc > 8) {
+    int32_t n_loaded = 0;
+    if (ffv_load_tuning(net, argv[8], &n_loaded) != FFV_OK) {
+      std::fprintf(stderr, "ffv_load_tuning: %s\n", ffv_last_error());
+      ffv_destroy_net(net);
+      return 1;
+    }
+    std::printf("loaded %d conv tile choices from %s\n", n_loaded, argv[8]);
   }
   std::vector<ffv_pair> pairs(n_pairs);
   for (int i = 0; i < n_pairs; ++i) pairs[i] = {cams + i * img, cams + (i + 1) * img, H, W};
