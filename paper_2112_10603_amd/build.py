@@ -21,8 +21,11 @@ LIB = os.path.join(LIBDIR, "libffv.so")
 ARCH = "gfx950"
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
           f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
-# Packed fp32 ops are disabled for all device code.
-DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Packed fp32 ops are disabled for all device code. The conv epilogues index
+# their accumulator arrays only through fully unrolled loops; the raised
+# unroll limit keeps those arrays in registers instead of scratch memory.
+DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-mllvm", "-pragma-unroll-threshold=1000000"]
 
 
 def _hipcc() -> str:

@@ -27,7 +27,10 @@
 // Inside a K step, lane half h = lane/32 owns one half of the step's k
 // range; the MFMA's k positions are fed in that order for both operands, so
 // the sum over k is the full dot product whatever the instruction's internal
-// k order. Accumulation is fp32 in every precision.
+// k order. Accumulation is fp32 in every precision. Tiles with 128 or 256
+// output channels in bf16/fp8 feed the weights as the MFMA's A operand, so
+// a lane ends with consecutive output channels of one pixel; their
+// epilogue stages the output tile through LDS and writes 16-byte chunks.
 #pragma once
 
 #include "common.h"
@@ -110,8 +113,10 @@ __device__ inline void store_out(const ConvArgs& a, long off, int o, float v) {
     *p = v;
   } else if (a.out_scale) {
     reinterpret_cast<uint8_t*>(a.out)[off] = to_f8(v * a.out_scale[o]);
+  } else if constexpr (sizeof(T) == 4) {
+    reinterpret_cast<float*>(a.out)[off] = v;  // FP32 nets keep fp32 activations
   } else {
-    reinterpret_cast<bf16*>(a.out)[off] = (bf16)v;
+    reinterpret_cast<bf16*>(a.out)[off] = (bf16)v;  // bf16, and non-fp8 outputs of fp8 layers
   }
 }
 
@@ -146,16 +151,22 @@ struct Conv {
   __device__ static inline int logical_chunk(int row, int phys) { return phys ^ key(row); }
 };
 
-template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES, int SWZ>
+template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES, int SWZ, bool SW>
 __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   using C = Conv<T, BM, BN, WM, WN, KB, STAGES, SWZ>;
   constexpr int NT = C::NT, CH = C::CH, BK = C::BK, VEC = C::VEC;
+  // SW: the MFMAs take the weights as A (each lane then holds consecutive
+  // channels of one pixel) and the output tile is staged through LDS for
+  // 16-byte stores (bf16/fp8 outputs with 16-byte aligned channel runs);
+  // otherwise the pixels are A and lanes store from registers.
+  static_assert(!SW || sizeof(T) != 4, "staged epilogue: bf16 or fp8 outputs");
   constexpr int TM = C::TM, TN = C::TN, FM = C::FM, FN = C::FN;
   constexpr int A_IT = C::A_IT, B_IT = C::B_IT;
   constexpr int A_VECS = C::A_VECS, B_VECS = C::B_VECS;
 
-  __shared__ __attribute__((aligned(16))) uint4 As[STAGES][BM * CH];
-  __shared__ __attribute__((aligned(16))) uint4 Bs[STAGES][BN * CH];
+  __shared__ __attribute__((aligned(16))) uint4 smem[STAGES * (BM + BN) * CH];
+  uint4 (*As)[BM * CH] = reinterpret_cast<uint4 (*)[BM * CH]>(smem);
+  uint4 (*Bs)[BN * CH] = reinterpret_cast<uint4 (*)[BN * CH]>(smem + STAGES * BM * CH);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -292,7 +303,12 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-          for (int j = 0; j < FN; ++j) mfma_f8(acc[i][j], fa[i][0], fa[i][1], fb[j][0], fb[j][1]);
+          for (int j = 0; j < FN; ++j) {
+            if constexpr (SW)
+              mfma_f8(acc[i][j], fb[j][0], fb[j][1], fa[i][0], fa[i][1]);
+            else
+              mfma_f8(acc[i][j], fa[i][0], fa[i][1], fb[j][0], fb[j][1]);
+          }
       }
     } else {
 #pragma unroll
@@ -306,7 +322,12 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-          for (int j = 0; j < FN; ++j) mfma_chunk<T>(acc[i][j], fa[i], fb[j]);
+          for (int j = 0; j < FN; ++j) {
+            if constexpr (SW)
+              mfma_chunk<T>(acc[i][j], fb[j], fa[i]);
+            else
+              mfma_chunk<T>(acc[i][j], fa[i], fb[j]);
+          }
       }
     }
   };
@@ -330,51 +351,140 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
     compute(kc % STAGES);
   }
 
-  // Epilogue: bias, ReLU, optional accumulate, store (NHWC, channel slice).
-  const int cout_m = merged ? a.cout : 1;
+  if constexpr (!SW) {
+    // Epilogue (pixels as A): lane l holds channel l%32 of fragment j for 16
+    // pixels; bias, ReLU, optional accumulate, store (NHWC, channel slice).
+    const int cout_m = merged ? a.cout : 1;
 #pragma unroll
-  for (int i = 0; i < FM; ++i) {
-    long off_row[16];
-    bool row_ok[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int row = wm * TM + i * 32 + (e >> 2) * 8 + lhalf * 4 + (e & 3);
-      int oy = ty0 + row / TW;
-      int ox = tx0 + row % TW;
-      row_ok[e] = oy < a.Ho && ox < a.Wo;
-      if (a.transposed) {  // output of the GEMM grid point (oy, ox), phase (0, 0)
-        oy *= 2;
-        ox *= 2;
-      }
-      off_row[e] = (long)img_t * a.out_img_stride + ((long)(oy + py) * a.Wout + ox + px) * a.out_ld;
-    }
-#pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      const int n = n0 + wn * TN + j * 32 + lrow;
-      long col;
-      int o;
-      if (!merged) {
-        if (n >= a.cout) continue;
-        o = n;
-        col = n;
-      } else {
-        if (n >= 4 * cout_m) continue;
-        const int ph = n / cout_m;
-        o = n - ph * cout_m;
-        col = ((long)(ph >> 1) * a.Wout + (ph & 1)) * a.out_ld + o;
-      }
-      const float bn = a.bias[o];
-      const float ws = a.w_scale ? a.w_scale[o] : 1.f;
-      float amax = 0.f;
+    for (int i = 0; i < FM; ++i) {
+      long off_row[16];
+      bool row_ok[16];
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        if (!row_ok[e]) continue;
-        float v = acc[i][j][e] * ws + bn;
-        if (a.relu) v = fmaxf(v, 0.f);
-        amax = fmaxf(amax, fabsf(v));
-        store_out<T>(a, off_row[e] + col, o, v);
+        const int row = wm * TM + i * 32 + (e >> 2) * 8 + lhalf * 4 + (e & 3);
+        int oy = ty0 + row / TW;
+        int ox = tx0 + row % TW;
+        row_ok[e] = oy < a.Ho && ox < a.Wo;
+        if (a.transposed) {  // output of the GEMM grid point (oy, ox), phase (0, 0)
+          oy *= 2;
+          ox *= 2;
+        }
+        off_row[e] = (long)img_t * a.out_img_stride + ((long)(oy + py) * a.Wout + ox + px) * a.out_ld;
       }
-      if (a.amax) atomicMax(reinterpret_cast<unsigned*>(a.amax) + o, __float_as_uint(amax));
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int n = n0 + wn * TN + j * 32 + lrow;
+        long col;
+        int o;
+        if (!merged) {
+          if (n >= a.cout) continue;
+          o = n;
+          col = n;
+        } else {
+          if (n >= 4 * cout_m) continue;
+          const int ph = n / cout_m;
+          o = n - ph * cout_m;
+          col = ((long)(ph >> 1) * a.Wout + (ph & 1)) * a.out_ld + o;
+        }
+        const float bn = a.bias[o];
+        const float ws = a.w_scale ? a.w_scale[o] : 1.f;
+        float amax = 0.f;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          if (!row_ok[e]) continue;
+          float v = acc[i][j][e] * ws + bn;
+          if (a.relu) v = fmaxf(v, 0.f);
+          amax = fmaxf(amax, fabsf(v));
+          store_out<T>(a, off_row[e] + col, o, v);
+        }
+        if (a.amax) atomicMax(reinterpret_cast<unsigned*>(a.amax) + o, __float_as_uint(amax));
+      }
+    }
+  } else {
+    // Epilogue (weights as A): lane l holds, for fragment (i, j), pixel
+    // i*32 + l%32 of the wave tile and channels j*32 + 8g + 4*(l/32) + q
+    // (g, q = 0..3). Bias, scale and ReLU are applied in registers; the
+    // wave's TM x TN output tile is written to its own LDS region (rows
+    // XOR-swizzled in 16-byte chunks) and read back row by row, so each
+    // global store moves 16 contiguous bytes per lane and whole pixel rows
+    // per group of lanes.
+    const int E = a.out_scale ? 1 : 2;  // output element bytes (fp8 or bf16)
+    static_assert(BM * BN * 2 <= STAGES * (BM + BN) * KB, "staged tile fits the LDS rings");
+    {
+      __syncthreads();  // every wave is done reading the A/B rings
+      const int pitch = TN * E;         // bytes per pixel row of the wave tile
+      const int cpr = pitch / 16;       // 16-byte chunks per row (a power of two)
+      char* region = reinterpret_cast<char*>(smem) + (size_t)wave * TM * TN * 2;
+      // channel-group major, so only one group's bias and scale are live
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int c0 = j * 32 + 8 * g + 4 * lhalf;  // channel within the wave tile
+          const int n = n0 + wn * TN + c0;
+          const bool nok = n < a.cout;  // cout is a multiple of 8: all four or none
+          const int nb = nok ? n : 0;
+          const float4 bias4 = *reinterpret_cast<const float4*>(a.bias + nb);
+          const float4 ws4 = a.w_scale ? *reinterpret_cast<const float4*>(a.w_scale + nb)
+                                       : make_float4(1.f, 1.f, 1.f, 1.f);
+          const float bq[4] = {bias4.x, bias4.y, bias4.z, bias4.w};
+          const float sq[4] = {ws4.x, ws4.y, ws4.z, ws4.w};
+          float os[4] = {1.f, 1.f, 1.f, 1.f};
+          if (E == 1) {
+            const float4 o4 = *reinterpret_cast<const float4*>(a.out_scale + nb);
+            os[0] = o4.x;
+            os[1] = o4.y;
+            os[2] = o4.z;
+            os[3] = o4.w;
+          }
+#pragma unroll
+          for (int i = 0; i < FM; ++i) {
+            const int p = i * 32 + lrow;
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              float x = acc[i][j][4 * g + q] * sq[q] + bq[q];
+              if (a.relu) x = fmaxf(x, 0.f);
+              if (a.amax && nok)
+                atomicMax(reinterpret_cast<unsigned*>(a.amax) + n + q, __float_as_uint(fabsf(x)));
+              v[q] = x;
+            }
+            const int byte = c0 * E;
+            const int chunk = (byte >> 4) ^ (p & (cpr - 1));
+            char* dst = region + p * pitch + chunk * 16 + (byte & 15);
+            if (E == 2) {
+              const bf16 b0 = (bf16)v[0], b1 = (bf16)v[1], b2 = (bf16)v[2], b3 = (bf16)v[3];
+              uint2 w;
+              w.x = (uint32_t)__builtin_bit_cast(uint16_t, b0) |
+                    ((uint32_t)__builtin_bit_cast(uint16_t, b1) << 16);
+              w.y = (uint32_t)__builtin_bit_cast(uint16_t, b2) |
+                    ((uint32_t)__builtin_bit_cast(uint16_t, b3) << 16);
+              *reinterpret_cast<uint2*>(dst) = w;
+            } else {
+              uint32_t w = 0;
+#pragma unroll
+              for (int q = 0; q < 4; ++q) w |= (uint32_t)to_f8(v[q] * os[q]) << (8 * q);
+              *reinterpret_cast<uint32_t*>(dst) = w;
+            }
+          }
+        }
+      }
+      __syncthreads();  // the region is read back by other lanes of the wave
+      for (int q = lane; q < TM * cpr; q += 64) {
+        const int p = q / cpr, ch = q - p * cpr;
+        const int row = wm * TM + p;
+        int oy = ty0 + row / TW;
+        int ox = tx0 + row % TW;
+        const int n = n0 + wn * TN + ch * (16 / E);
+        if (oy >= a.Ho || ox >= a.Wo || n >= a.cout) continue;
+        if (a.transposed) {
+          oy *= 2;
+          ox *= 2;
+        }
+        const long off = (long)img_t * a.out_img_stride + ((long)(oy + py) * a.Wout + ox + px) * a.out_ld + n;
+        const uint4 w = *reinterpret_cast<const uint4*>(region + p * pitch + ((ch ^ (p & (cpr - 1))) * 16));
+        *reinterpret_cast<uint4*>(reinterpret_cast<char*>(a.out) + off * E) = w;
+      }
     }
   }
 }
@@ -392,7 +502,18 @@ hipError_t launch_variant(const ConvArgs& a, hipStream_t s) {
                      ((a.Wo + a.tile_w - 1) / a.tile_w);
   if (tiles > 0x7fffffffL) return hipErrorInvalidValue;
   dim3 grid((unsigned)tiles, (unsigned)n_tiles, phases);
-  hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES, SWZ>), grid, dim3(C::NT), 0, s, a);
+  // the staged epilogue needs bf16/fp8 outputs in 16-byte channel runs
+  const int run = a.out_scale ? 16 : 8;
+  const bool staged = sizeof(T) != 4 && BN >= 128 && a.transposed != 2 && !a.out_f32 &&
+                      a.cout % run == 0 && a.out_ld % run == 0;
+  if constexpr (sizeof(T) != 4 && BN >= 128) {
+    if (staged) {
+      hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES, SWZ, true>), grid, dim3(C::NT), 0, s,
+                         a);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES, SWZ, false>), grid, dim3(C::NT), 0, s, a);
   return hipGetLastError();
 }
 
