@@ -164,13 +164,17 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   constexpr int A_IT = C::A_IT, B_IT = C::B_IT;
   constexpr int A_VECS = C::A_VECS, B_VECS = C::B_VECS;
 
-  __shared__ __attribute__((aligned(16))) uint4 smem[STAGES * (BM + BN) * CH];
+  // the A/B rings, reused by the staged epilogue (BM x BN 2-byte values)
+  constexpr int RING_VECS = STAGES * (BM + BN) * CH;
+  constexpr int SMEM_VECS = (SW && BM * BN * 2 / 16 > RING_VECS) ? BM * BN * 2 / 16 : RING_VECS;
+  __shared__ __attribute__((aligned(16))) uint4 smem[SMEM_VECS];
   uint4 (*As)[BM * CH] = reinterpret_cast<uint4 (*)[BM * CH]>(smem);
   uint4 (*Bs)[BN * CH] = reinterpret_cast<uint4 (*)[BN * CH]>(smem + STAGES * BM * CH);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  // uniform, so LDS destinations and per-wave offsets live in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WN, wn = wave % WN;
   const int merged = a.transposed == 2;
   const int phase = a.transposed == 1 ? (int)blockIdx.z : 0;
@@ -196,82 +200,95 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   const T* wgt = reinterpret_cast<const T*>(a.wgt) + (long)phase * a.cout_pad * a.K_pad;
   (void)VEC;
 
-  // Per A-load row data, fixed across the K loop. Load i of this thread
-  // fills LDS slot tid + i*NT = (row, physical chunk tid % CH).
-  const T* a_base[A_IT];
-  int a_iy[A_IT], a_ix[A_IT], a_ch[A_IT];
-  bool a_ok[A_IT];
+  // a step stays inside one tap when the channel count is a multiple of BK
+  const bool tap_uniform = (a.cin_pad % BK) == 0;
+  // input offset of tap t: 3x3 neighbourhood, or the 2x2 taps of one
+  // transposed-conv output phase
+  auto tap_dy = [&](int t) { return a.transposed == 1 ? py - (t >> 1) : ((t * 11) >> 5) - 1; };
+  auto tap_dx = [&](int t) {
+    return a.transposed == 1 ? px - (t & 1) : t - 3 * (((t * 11) >> 5)) - 1;
+  };
+
+  // Per A-load data, fixed across the K loop. Load i of this thread fills
+  // LDS slot tid + i*NT = (row, physical chunk tid % CH): the pixel's offset
+  // in its image, a bit mask of the taps whose sample lies inside the image
+  // (none for rows past the grid), and for tap-major K order the running
+  // (tap, channel) of this load's k.
+  const T* a_ptr[A_IT];
+  int a_pix[A_IT], a_tap[A_IT], a_c[A_IT];
+  uint32_t a_mask[A_IT];
 #pragma unroll
   for (int i = 0; i < A_IT; ++i) {
     const int v = tid + i * NT;
     const int row = v / CH;
     const int oy = ty0 + row / TW, ox = tx0 + row % TW;
-    a_ok[i] = (v < A_VECS) && (oy < a.Ho) && (ox < a.Wo);
-    a_base[i] = in + (long)img_t * a.in_img_stride;
-    a_iy[i] = oy * a.stride;
-    a_ix[i] = ox * a.stride;
-    a_ch[i] = C::logical_chunk(row, chunk);
+    const bool ok = (v < A_VECS) && (oy < a.Ho) && (ox < a.Wo);
+    const int iy0 = oy * a.stride, ix0 = ox * a.stride;
+    const int kk = C::logical_chunk(row, chunk) * VEC;
+    a_ptr[i] = in + (long)img_t * a.in_img_stride + (tap_uniform ? kk : 0);
+    a_pix[i] = (iy0 * a.Wi + ix0) * a.in_ld;
+    uint32_t m = 0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int iy = iy0 + tap_dy(t), ix = ix0 + tap_dx(t);
+      if (ok && t < a.taps && iy >= 0 && iy < a.Hi && ix >= 0 && ix < a.Wi) m |= 1u << t;
+    }
+    a_mask[i] = m;
+    a_tap[i] = kk / a.cin_pad;
+    a_c[i] = kk - a_tap[i] * a.cin_pad;
   }
-  const T* b_row[B_IT];
-  int b_ch[B_IT];
+  const T* b_ptr[B_IT];
 #pragma unroll
   for (int i = 0; i < B_IT; ++i) {
     const int v = tid + i * NT;
     const int row = (B_VECS % NT == 0 || v < B_VECS) ? v / CH : 0;
-    b_row[i] = wgt + (long)(n0 + row) * a.K_pad;
-    b_ch[i] = C::logical_chunk(row, chunk);
+    b_ptr[i] = wgt + (long)(n0 + row) * a.K_pad + C::logical_chunk(row, chunk) * VEC;
   }
   const T* zero = reinterpret_cast<const T*>(a.zero);
   const int nk = a.K_pad / BK;
   const int lrow = lane & 31;
   const int lhalf = lane >> 5;
-  // a step stays inside one tap when the channel count is a multiple of BK
-  const bool tap_uniform = (a.cin_pad % BK) == 0;
+  const int step_taps = BK / a.cin_pad, step_c = BK - step_taps * a.cin_pad;
 
+  // Issue the loads of K step kc into ring buffer buf. Steps are issued in
+  // increasing order, one at a time (the tap-major counters advance here).
   auto issue = [&](int kc, int buf) {
-    // K order: when a step stays inside one tap (channels a multiple of BK)
-    // the steps run channel-slice major, all taps of a slice back to back,
-    // so the input lines a slice needs are reused while still in L2;
-    // otherwise tap major. The packed weights use the same order.
-    int tap_u = 0, c_u = 0;
     if (tap_uniform) {
+      // channel-slice major: all taps of a BK-channel slice back to back, so
+      // the input lines of a slice are reused while still in L2 (the packed
+      // weights use the same order); tap and slice are uniform
       const int slice = kc / a.taps;
-      tap_u = kc - slice * a.taps;
-      c_u = slice * BK;
-    }
+      const int tap = kc - slice * a.taps;
+      const int c_u = slice * BK;
+      const bool kin = c_u < a.cin_pad;  // steps past the real K read nothing
+      const int toff = (tap_dy(tap) * a.Wi + tap_dx(tap)) * a.in_ld + c_u;
 #pragma unroll
-    for (int i = 0; i < A_IT; ++i) {
-      const int kk = a_ch[i] * VEC;
-      int tap, c;
-      if (tap_uniform) {
-        tap = tap_u;
-        c = c_u + kk;
-      } else {
-        const int k0 = kc * BK + kk;
-        tap = k0 < a.K ? k0 / a.cin_pad : 9;
-        c = k0 - (k0 < a.K ? tap : 0) * a.cin_pad;
+      for (int i = 0; i < A_IT; ++i) {
+        const bool ok = kin && ((a_mask[i] >> tap) & 1u);
+        const T* src = ok ? a_ptr[i] + (a_pix[i] + toff) : zero;
+        if (A_VECS % NT == 0 || tid + i * NT < A_VECS) load_to_lds(src, &As[buf][i * NT + wave * 64]);
       }
-      int dy, dx;
-      if (a.transposed == 1) {
-        dy = py - (tap >> 1);
-        dx = px - (tap & 1);
-      } else {
-        dy = tap / 3 - 1;
-        dx = tap - (tap / 3) * 3 - 1;
+    } else {
+      // tap major: a step spans several taps; each load follows its own k
+#pragma unroll
+      for (int i = 0; i < A_IT; ++i) {
+        const int tap = a_tap[i];  // >= taps once k passes the real K: mask bit 0
+        const bool ok = (a_mask[i] >> tap) & 1u;
+        const int toff = (tap_dy(tap) * a.Wi + tap_dx(tap)) * a.in_ld + a_c[i];
+        const T* src = ok ? a_ptr[i] + (a_pix[i] + toff) : zero;
+        if (A_VECS % NT == 0 || tid + i * NT < A_VECS) load_to_lds(src, &As[buf][i * NT + wave * 64]);
+        a_c[i] += step_c;
+        a_tap[i] += step_taps;
+        if (a_c[i] >= a.cin_pad) {
+          a_c[i] -= a.cin_pad;
+          a_tap[i] += 1;
+        }
       }
-      const int iy = a_iy[i] + dy, ix = a_ix[i] + dx;
-      // steps past the real K (K padded to the step) read nothing
-      const bool kin = tap_uniform ? c_u < a.cin_pad : tap < a.taps;
-      const bool ok = a_ok[i] && kin && iy >= 0 && iy < a.Hi && ix >= 0 && ix < a.Wi;
-      const T* src = ok ? a_base[i] + ((long)iy * a.Wi + ix) * a.in_ld + c : zero;
-      if (A_VECS % NT == 0 || tid + i * NT < A_VECS)
-        load_to_lds(src, &As[buf][i * NT + wave * 64]);
     }
 #pragma unroll
     for (int i = 0; i < B_IT; ++i) {
-      const T* src = b_row[i] + (long)kc * BK + b_ch[i] * VEC;
-      if (B_VECS % NT == 0 || tid + i * NT < B_VECS)
-        load_to_lds(src, &Bs[buf][i * NT + wave * 64]);
+      const T* src = b_ptr[i] + (long)kc * BK;
+      if (B_VECS % NT == 0 || tid + i * NT < B_VECS) load_to_lds(src, &Bs[buf][i * NT + wave * 64]);
     }
   };
 
@@ -409,7 +426,6 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
     // global store moves 16 contiguous bytes per lane and whole pixel rows
     // per group of lanes.
     const int E = a.out_scale ? 1 : 2;  // output element bytes (fp8 or bf16)
-    static_assert(BM * BN * 2 <= STAGES * (BM + BN) * KB, "staged tile fits the LDS rings");
     {
       __syncthreads();  // every wave is done reading the A/B rings
       const int pitch = TN * E;         // bytes per pixel row of the wave tile
@@ -501,6 +517,8 @@ hipError_t launch_variant(const ConvArgs& a, hipStream_t s) {
   const long tiles = (long)a.n_img * ((a.Ho + BM / a.tile_w - 1) / (BM / a.tile_w)) *
                      ((a.Wo + a.tile_w - 1) / a.tile_w);
   if (tiles > 0x7fffffffL) return hipErrorInvalidValue;
+  // per-image input offsets are 32-bit in the kernel
+  if ((long)a.Hi * a.Wi * a.in_ld >= (1L << 31)) return hipErrorInvalidValue;
   dim3 grid((unsigned)tiles, (unsigned)n_tiles, phases);
   // the staged epilogue needs bf16/fp8 outputs in 16-byte channel runs
   const int run = a.out_scale ? 16 : 8;
