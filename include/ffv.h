@@ -245,7 +245,9 @@ ffv_status ffv_kernel_stats(ffv_net* net, const char* name, int64_t* launches, d
  *           (conv) or 2h (transposed)
  * precision: FFV_FP32 or FFV_BF16 (inputs and weights rounded to bf16, fp32
  * accumulation and output). n_tile (0 = the layer's default, else 256, 128,
- * 64 or 32 output channels per workgroup) and tile_w (0 = default, else the
+ * 64 or 32 output channels per workgroup, or 1 = the halo-reuse kernel:
+ * 32 channels of a 16x16 pixel block, for stride-1 convs whose input
+ * channels are a multiple of the K step) and tile_w (0 = default, else the
  * width of the 256-pixel block of a workgroup, a divisor of 256) pick the
  * kernel variant, as autotuning does; every choice gives the same result.
  * Allocates temporaries; synchronises `stream`.

@@ -275,8 +275,8 @@ extern "C" ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, 
   if (precision != FFV_FP32 && precision != FFV_BF16) return fail(FFV_ERR_ARG, "precision");
   if (n <= 0 || cin <= 0 || h <= 0 || w <= 0 || cout <= 0) return fail(FFV_ERR_ARG, "sizes");
   if (!transposed && stride != 1 && stride != 2) return fail(FFV_ERR_ARG, "stride");
-  if (n_tile != 0 && n_tile != 32 && n_tile != 64 && n_tile != 128 && n_tile != 256)
-    return fail(FFV_ERR_ARG, "n_tile must be 0, 32, 64, 128 or 256");
+  if (n_tile != 0 && n_tile != 1 && n_tile != 32 && n_tile != 64 && n_tile != 128 && n_tile != 256)
+    return fail(FFV_ERR_ARG, "n_tile must be 0, 1, 32, 64, 128 or 256");
   if (tile_w < 0 || tile_w > 256 || (tile_w > 0 && 256 % tile_w != 0))
     return fail(FFV_ERR_ARG, "tile_w must be 0 or divide 256");
   const DType dt = precision == FFV_FP32 ? DType::F32 : DType::BF16;
@@ -347,6 +347,10 @@ extern "C" ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, 
     if (n_tile == 128) tile = ConvTile::N128;
     if (n_tile == 64) tile = ConvTile::N64;
     if (n_tile == 32) tile = ConvTile::N32;
+    if (n_tile == 1) {
+      tile = ConvTile::H32;
+      a.tile_w = 16;
+    }
     err = launch_conv(dt, tile, a, s);
   }
   for (int i = 0; err == hipSuccess && i < n; ++i)

@@ -62,8 +62,12 @@ struct ConvArgs {
   const void* zero;     // >= 16 bytes of zeros (read for taps outside the image)
 };
 
-// N-tile widths the conv kernel is instantiated for (the M tile is 256).
-enum class ConvTile : int { N256 = 0, N128 = 1, N64 = 2, N32 = 3 };
+// N-tile widths the conv kernel is instantiated for (the M tile is 256), and
+// H32: the halo-reuse kernel (16x16 output pixels x 32 channels, stride-1
+// 3x3 neighbourhoods only; the M-tile width must be 16).
+enum class ConvTile : int { N256 = 0, N128 = 1, N64 = 2, N32 = 3, H32 = 4 };
+// Whether the halo-reuse kernel can run a launch (tile_w is not checked).
+bool conv_halo_ok(DType dt, const ConvArgs& a);
 
 hipError_t launch_conv(DType dt, ConvTile tile, const ConvArgs& a, hipStream_t s);
 // Width of the 2-D pixel block of a 256-pixel M tile for a Ho x Wo grid:

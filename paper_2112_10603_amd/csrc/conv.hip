@@ -1,6 +1,8 @@
 // Instantiations of the implicit-GEMM convolution kernel (conv_kernel.h)
-// used by the library, one per N-tile class. All use 128-byte K steps
-// (conv_k_step), which the weight packing's K order depends on.
+// used by the library, one per N-tile class, and of the halo-reuse kernel
+// (conv_halo.h). All use 128-byte K steps (conv_k_step), which the weight
+// packing's K order depends on.
+#include "conv_halo.h"
 #include "conv_kernel.h"
 
 namespace ffv {
@@ -19,6 +21,8 @@ hipError_t launch_t(ConvTile tile, const ConvArgs& a, hipStream_t s) {
       return launch_variant<T, 256, 64, 8, 1, 128, 2, 1>(a, s);
     case ConvTile::N32:
       return launch_variant<T, 256, 32, 8, 1, 128, 2, 1>(a, s);
+    case ConvTile::H32:
+      return launch_halo<T>(a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -26,6 +30,12 @@ hipError_t launch_t(ConvTile tile, const ConvArgs& a, hipStream_t s) {
 }  // namespace
 
 int conv_k_step(DType dt) { return dt == DType::F32 ? 32 : (dt == DType::BF16 ? 64 : 128); }
+
+bool conv_halo_ok(DType dt, const ConvArgs& a) {
+  ConvArgs b = a;
+  b.tile_w = convk::Halo::TW;
+  return convk::halo_ok(b, conv_k_step(dt));
+}
 
 int conv_tile_width(int Ho, int Wo) {
   int best = 16;

@@ -499,6 +499,30 @@ void Net::set_profiling(bool on) {
   stats_.clear();
 }
 
+// Record e on x's stream. Under capture the record becomes an event-record
+// node of the graph, appended after the nodes captured so far, so the event
+// is timestamped on every replay.
+void Net::record_event(const Exec& x, hipEvent_t e) {
+  if (!x.capture) {
+    hipEventRecord(e, x.s);
+    return;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  unsigned long long id = 0;
+  hipGraph_t graph = nullptr;
+  const hipGraphNode_t* deps = nullptr;
+  size_t n_deps = 0;
+  if (hipStreamGetCaptureInfo_v2(x.s, &cs, &id, &graph, &deps, &n_deps) != hipSuccess ||
+      cs != hipStreamCaptureStatusActive) {
+    prof_error_ = true;
+    return;
+  }
+  hipGraphNode_t node = nullptr;
+  if (hipGraphAddEventRecordNode(&node, graph, deps, n_deps, e) != hipSuccess ||
+      hipStreamUpdateCaptureDependencies(x.s, &node, 1, hipStreamSetCaptureDependencies) != hipSuccess)
+    prof_error_ = true;
+}
+
 void Net::prof_begin(const Exec& x) {
   if (!x.prof) return;
   hipEvent_t e;
@@ -508,7 +532,7 @@ void Net::prof_begin(const Exec& x) {
   } else {
     hipEventCreate(&e);
   }
-  hipEventRecord(e, x.s);
+  record_event(x, e);
   cur_start_ = e;
 }
 
@@ -521,7 +545,7 @@ void Net::prof_end(const Exec& x, const char* cls, double work) {
   } else {
     hipEventCreate(&e);
   }
-  hipEventRecord(e, x.s);
+  record_event(x, e);
   pending_.push_back({cur_start_, e, cls, work});
   cur_start_ = nullptr;
 }
@@ -585,6 +609,11 @@ Status Net::conv(const Exec& x, const Layer& L, const void* in, int in_ld, long 
   a.tile_w = conv_tile_width(a.Ho, a.Wo);
   ConvTile tile = L.tile;
   const DType kdt = in_fp8 ? DType::FP8 : dt_;
+  // few output channels over a stride-1 3x3 neighbourhood: the halo kernel
+  if (L.rows <= 32 && conv_halo_ok(kdt, a)) {
+    tile = ConvTile::H32;
+    a.tile_w = 16;
+  }
   if (!tuned_.empty() || recording_) {
     const TuneKey key{L.name, in_fp8 ? 1 : 0, a.Ho, a.Wo, n_img};
     auto it = tuned_.find(key);
@@ -891,6 +920,7 @@ Status Net::interpolate_locked(const float* const* left, const float* const* rig
     FFV_TRY(check(hipMemcpyAsync(view_tab, vd.data(), sizeof(ViewDesc) * n_view_total,
                                  hipMemcpyHostToDevice, stream_),
                   "copy view table"));
+  x.capture = use_graph;
   Exec xv = x;
   xv.ws = base + fixed;
   auto launch_all = [&]() -> Status {
@@ -908,7 +938,9 @@ Status Net::interpolate_locked(const float* const* left, const float* const* rig
     if (it == graph_cache_.end()) {
       pending_.clear();
       FFV_TRY(check(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal), "begin capture"));
-      const Status st = launch_all();
+      prof_error_ = false;
+      Status st = launch_all();
+      if (st.good() && prof_error_) st = Status::err(-4, "profiling: event-record node in graph capture");
       hipGraph_t graph = nullptr;
       const hipError_t ec = hipStreamEndCapture(stream_, &graph);
       GraphEntry entry;
@@ -1111,7 +1143,8 @@ Status Net::autotune(const float* const* left, const float* const* right, int n_
   FFV_TRY(check(hipEventCreate(&e0), "hipEventCreate"));
   Status res = check(hipEventCreate(&e1), "hipEventCreate");
   std::map<TuneKey, TuneVal> found;
-  const ConvTile tiles[4] = {ConvTile::N256, ConvTile::N128, ConvTile::N64, ConvTile::N32};
+  const ConvTile tiles[5] = {ConvTile::N256, ConvTile::N128, ConvTile::N64, ConvTile::N32,
+                             ConvTile::H32};
   const int widths[4] = {8, 16, 32, 64};
   for (size_t r = 0; res.good() && r < recs_.size(); ++r) {
     const TuneRec& rec = recs_[r];
@@ -1125,13 +1158,16 @@ Status Net::autotune(const float* const* left, const float* const* right, int n_
     }
     float best_ms = -1.f;
     TuneVal best{};
-    for (int ti = 0; res.good() && ti < 4; ++ti) {
-      const int bn = 256 >> ti;
+    for (int ti = 0; res.good() && ti < 5; ++ti) {
+      const bool halo = tiles[ti] == ConvTile::H32;
+      const int bn = halo ? 32 : 256 >> ti;
       if (bn >= 2 * rows32) continue;  // at least half of every tile's columns real
+      if (halo && !conv_halo_ok(rec.dt, rec.a)) continue;
       for (int tw : widths) {
+        if (halo && tw != 16) continue;  // the halo kernel's block is 16 x 16
         const int th = 256 / tw;
         const long area = (long)((rec.a.Ho + th - 1) / th) * th * ((rec.a.Wo + tw - 1) / tw) * tw;
-        if (area * 10 > min_area * 11) continue;  // within 10 % of the least padding
+        if (!halo && area * 10 > min_area * 11) continue;  // within 10 % of the least padding
         ConvArgs a = rec.a;
         a.tile_w = tw;
         a.amax = nullptr;
@@ -1166,7 +1202,9 @@ Status Net::autotune(const float* const* left, const float* const* right, int n_
   return Status::ok();
 }
 
-static int tile_bn(ConvTile t) { return 256 >> (int)t; }
+static std::string tile_name(ConvTile t) {
+  return t == ConvTile::H32 ? std::string("h32") : std::to_string(256 >> (int)t);
+}
 
 Status Net::save_tuning(const std::string& path) {
   std::lock_guard<std::mutex> lk(call_mu_);
@@ -1174,8 +1212,8 @@ Status Net::save_tuning(const std::string& path) {
   if (!f) return Status::err(-1, "cannot open " + path + " for writing");
   std::fprintf(f, "# ffv conv tuning v1: layer fp8 Ho Wo n_img n_tile tile_w\n");
   for (auto& kv : tuned_)
-    std::fprintf(f, "%s %d %d %d %d %d %d\n", kv.first.layer.c_str(), kv.first.fp8, kv.first.Ho,
-                 kv.first.Wo, kv.first.n_img, tile_bn(kv.second.tile), kv.second.tile_w);
+    std::fprintf(f, "%s %d %d %d %d %s %d\n", kv.first.layer.c_str(), kv.first.fp8, kv.first.Ho,
+                 kv.first.Wo, kv.first.n_img, tile_name(kv.second.tile).c_str(), kv.second.tile_w);
   const bool ok = std::fclose(f) == 0;
   return ok ? Status::ok() : Status::err(-1, "write failed: " + path);
 }
@@ -1192,22 +1230,31 @@ Status Net::load_tuning(const std::string& path, int* n_loaded) {
   while (std::fgets(line, sizeof line, f)) {
     ++lineno;
     if (line[0] == '#' || line[0] == '\n') continue;
-    char name[256];
-    int fp8, ho, wo, n, bn, tw;
-    if (std::sscanf(line, "%255s %d %d %d %d %d %d", name, &fp8, &ho, &wo, &n, &bn, &tw) != 7 ||
-        (fp8 != 0 && fp8 != 1) || ho <= 0 || wo <= 0 || n <= 0 ||
-        (bn != 256 && bn != 128 && bn != 64 && bn != 32) || tw <= 0 || tw > 256 || 256 % tw != 0 ||
+    char name[256], tname[16];
+    int fp8, ho, wo, n, tw;
+    if (std::sscanf(line, "%255s %d %d %d %d %15s %d", name, &fp8, &ho, &wo, &n, tname, &tw) != 7 ||
+        (fp8 != 0 && fp8 != 1) || ho <= 0 || wo <= 0 || n <= 0 || tw <= 0 || tw > 256 || 256 % tw != 0 ||
         !layers_.count(name)) {
       st = Status::err(-1, path + ": bad entry on line " + std::to_string(lineno));
       break;
     }
+    const std::string tn = tname;
+    ConvTile t;
+    if (tn == "256") t = ConvTile::N256;
+    else if (tn == "128") t = ConvTile::N128;
+    else if (tn == "64") t = ConvTile::N64;
+    else if (tn == "32") t = ConvTile::N32;
+    else if (tn == "h32" && tw == 16) t = ConvTile::H32;
+    else {
+      st = Status::err(-1, path + ": bad tile on line " + std::to_string(lineno));
+      break;
+    }
+    const int bn = t == ConvTile::H32 ? 32 : 256 >> (int)t;
     const Layer& L = layers_.at(name);
     if (L.name == "unet.head" || bn > L.cout_pad) {
       st = Status::err(-1, path + ": entry on line " + std::to_string(lineno) + " does not fit its layer");
       break;
     }
-    const ConvTile t = bn == 256 ? ConvTile::N256
-                                 : (bn == 128 ? ConvTile::N128 : (bn == 64 ? ConvTile::N64 : ConvTile::N32));
     got[TuneKey{name, fp8, ho, wo, n}] = TuneVal{t, tw};
   }
   std::fclose(f);

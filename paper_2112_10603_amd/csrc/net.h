@@ -87,6 +87,7 @@ struct Exec {
   hipStream_t s = nullptr;
   char* ws = nullptr;
   bool prof = false;
+  bool capture = false;  // the stream is being captured into a graph
   char* at(size_t off) const { return ws + off; }
 };
 
@@ -171,6 +172,8 @@ class Net {
   Status quantize_vib_layers();
   const Layer& layer(const std::string& n) const { return layers_.at(n); }
   void prof_begin(const Exec& x);
+  void record_event(const Exec& x, hipEvent_t e);
+  bool prof_error_ = false;  // an event-record node could not be added
   void prof_end(const Exec& x, const char* cls, double work);
 
   std::map<std::string, Layer> layers_;

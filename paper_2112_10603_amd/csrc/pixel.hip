@@ -8,6 +8,8 @@
 // Sample positions, bilinear weights, flows and the mask stay fp32 in every
 // precision; only the activations fed to convolutions use the activation
 // dtype.
+#include <type_traits>
+
 #include "common.h"
 
 namespace ffv {
@@ -268,34 +270,66 @@ __global__ void ctx_warp_k(const ViewDesc* views, const CamDev* cams, int level,
 
 // ----------------------------------------------------------- output head
 // r = sigmoid(conv3x3(u4 -> 3)); out = clamp(I2 + 2r - 1, 0, 1), cropped and
-// written planar [3][H][W]. C (the U-Net's last width) is at most 64.
+// written planar [3][H][W]. C (the U-Net's last width) is a multiple of 8,
+// at most 64, and a template parameter: each tap's C channels arrive as
+// 16-byte vector loads, and the three output weights of a (tap, channel)
+// are one float4 in LDS (the same address in every lane: a broadcast).
 template <typename T>
-__global__ void head_k(const T* u4, int ld, int C, const float* wgt, const float* bias,
-                       const float* I2, const ViewDesc* views, int Hp, int Wp, int H, int W) {
-  __shared__ float ws[3 * 64 * 9 + 3];
-  const int nw = 3 * C * 9;
-  for (int i = threadIdx.x; i < nw; i += TPB) ws[i] = wgt[i];
-  if (threadIdx.x < 3) ws[nw + threadIdx.x] = bias[threadIdx.x];
+__device__ inline void load_chunk(const T* p, float (&v)[16 / sizeof(T)]);
+
+template <>
+__device__ inline void load_chunk<bf16>(const bf16* p, float (&v)[8]) {
+  const uint4 u = *reinterpret_cast<const uint4*>(p);
+  const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[2 * k] = __uint_as_float(w[k] << 16);
+    v[2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
+  }
+}
+
+template <>
+__device__ inline void load_chunk<float>(const float* p, float (&v)[4]) {
+  const float4 u = *reinterpret_cast<const float4*>(p);
+  v[0] = u.x;
+  v[1] = u.y;
+  v[2] = u.z;
+  v[3] = u.w;
+}
+
+template <typename T, int C>
+__global__ void head_k(const T* u4, int ld, const float* wgt, const float* bias, const float* I2,
+                       const ViewDesc* views, int Hp, int Wp, int H, int W) {
+  constexpr int V = 16 / (int)sizeof(T);  // channels per 16-byte load
+  static_assert(C % V == 0, "whole vector loads");
+  __shared__ float4 ws[9 * C];  // [tap][channel] -> (w_r, w_g, w_b, 0)
+  for (int i = threadIdx.x; i < 9 * C; i += TPB) {
+    const int tap = i / C, c = i - tap * C;
+    ws[i] = make_float4(wgt[(0 * C + c) * 9 + tap], wgt[(1 * C + c) * 9 + tap],
+                        wgt[(2 * C + c) * 9 + tap], 0.f);
+  }
   __syncthreads();
   const int v = blockIdx.y;
   const long p = (long)blockIdx.x * TPB + threadIdx.x;
   if (p >= (long)H * W) return;
   const int y = (int)(p / W), x = (int)(p % W);
   const T* base = u4 + (long)v * Hp * Wp * ld;
-  float z0 = ws[nw], z1 = ws[nw + 1], z2 = ws[nw + 2];
-  for (int dy = 0; dy < 3; ++dy) {
-    const int yy = y + dy - 1;
-    if (yy < 0 || yy >= Hp) continue;
-    for (int dx = 0; dx < 3; ++dx) {
-      const int xx = x + dx - 1;
-      if (xx < 0 || xx >= Wp) continue;
-      const T* s = base + ((long)yy * Wp + xx) * ld;
-      const int tap = dy * 3 + dx;
-      for (int c = 0; c < C; ++c) {
-        const float a = (float)s[c];
-        z0 += ws[(0 * C + c) * 9 + tap] * a;
-        z1 += ws[(1 * C + c) * 9 + tap] * a;
-        z2 += ws[(2 * C + c) * 9 + tap] * a;
+  float z0 = bias[0], z1 = bias[1], z2 = bias[2];
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) {
+    const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+    if (yy < 0 || yy >= Hp || xx < 0 || xx >= Wp) continue;  // zero padding
+    const T* s = base + ((long)yy * Wp + xx) * ld;
+#pragma unroll
+    for (int c0 = 0; c0 < C; c0 += V) {
+      float a[V];
+      load_chunk<T>(s + c0, a);
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        const float4 w = ws[tap * C + c0 + k];
+        z0 += w.x * a[k];
+        z1 += w.y * a[k];
+        z2 += w.z * a[k];
       }
     }
   }
@@ -423,13 +457,27 @@ hipError_t launch_head(const void* u4, int ld, int C, const float* w, const floa
                        const float* I2, const ViewDesc* views, int n_img, int Hp, int Wp, int H,
                        int W, DType dt, hipStream_t s) {
   if (n_img <= 0) return hipSuccess;
-  if (C > 64 || C > ld) return hipErrorInvalidValue;
-  if (dt == DType::F32)
-    hipLaunchKernelGGL(head_k<float>, grid1((long)H * W, n_img), dim3(TPB), 0, s,
-                       (const float*)u4, ld, C, w, b, I2, views, Hp, Wp, H, W);
-  else
-    hipLaunchKernelGGL(head_k<bf16>, grid1((long)H * W, n_img), dim3(TPB), 0, s,
-                       (const bf16*)u4, ld, C, w, b, I2, views, Hp, Wp, H, W);
+  if (C <= 0 || C > 64 || C % 8 != 0 || C > ld || ld % 8 != 0) return hipErrorInvalidValue;
+  const dim3 grid = grid1((long)H * W, n_img);
+  auto go = [&](auto tc) {
+    constexpr int CC = decltype(tc)::value;
+    if (dt == DType::F32)
+      hipLaunchKernelGGL((head_k<float, CC>), grid, dim3(TPB), 0, s, (const float*)u4, ld, w, b, I2, views,
+                         Hp, Wp, H, W);
+    else
+      hipLaunchKernelGGL((head_k<bf16, CC>), grid, dim3(TPB), 0, s, (const bf16*)u4, ld, w, b, I2, views,
+                         Hp, Wp, H, W);
+  };
+  switch (C) {
+    case 8: go(std::integral_constant<int, 8>{}); break;
+    case 16: go(std::integral_constant<int, 16>{}); break;
+    case 24: go(std::integral_constant<int, 24>{}); break;
+    case 32: go(std::integral_constant<int, 32>{}); break;
+    case 40: go(std::integral_constant<int, 40>{}); break;
+    case 48: go(std::integral_constant<int, 48>{}); break;
+    case 56: go(std::integral_constant<int, 56>{}); break;
+    default: go(std::integral_constant<int, 64>{}); break;
+  }
   return hipGetLastError();
 }
 

@@ -111,3 +111,50 @@ def test_conv_tile_variants_agree(cin, cout, h, w, stride, transposed):
             got = op_conv(xd, wt, b, stride=max(stride, 1), transposed=transposed, relu=True,
                           precision="bf16", n_tile=n_tile, tile_w=tile_w).cpu()
             assert torch.equal(got, base), (n_tile, tile_w, (got - base).abs().max().item())
+    halo = ((not transposed and stride == 1) or (transposed and cout <= 16)) and cin % 64 == 0
+    if halo:
+        got = op_conv(xd, wt, b, stride=max(stride, 1), transposed=transposed, relu=True,
+                      precision="bf16", n_tile=1).cpu()
+        assert torch.equal(got, base), ("halo", (got - base).abs().max().item())
+
+
+HALO_CASES = [
+    # (cin, cout, h, w, transposed): stride-1 3x3 convs and phase-merged
+    # transposed convs, ragged against the 16x16 block, several N tiles
+    (64, 16, 37, 45, False),
+    (128, 64, 20, 33, False),
+    (64, 40, 16, 16, False),
+    (128, 5, 23, 19, True),
+    (64, 16, 17, 31, True),
+    (192, 8, 9, 40, True),
+]
+
+
+@pytest.mark.parametrize("cin,cout,h,w,transposed", HALO_CASES)
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_conv_halo_kernel_vs_oracle(cin, cout, h, w, transposed, precision):
+    """The halo-reuse kernel (one input halo per channel slice, nine taps read
+    from LDS) against the oracle, on shapes where blocks straddle the image
+    border and the output grid is not a multiple of 16."""
+    from paper_2112_10603_amd import op_conv
+    print(f"case halo cin={cin} cout={cout} h={h} w={w} T={transposed} {precision}", flush=True)
+    rng = np.random.default_rng(cin * 31 + cout)
+    n = 3
+    x = rng.standard_normal((n, cin, h, w)).astype(np.float32)
+    if transposed:
+        wt = (rng.standard_normal((cin, cout, 4, 4)) / np.sqrt(4 * cin)).astype(np.float32)
+    else:
+        wt = (rng.standard_normal((cout, cin, 3, 3)) / np.sqrt(9 * cin)).astype(np.float32)
+    b = rng.standard_normal(cout).astype(np.float32)
+    if precision == "bf16":
+        xr = torch.from_numpy(x).bfloat16().double().numpy()
+        wr = torch.from_numpy(wt).bfloat16().double().numpy()
+    else:
+        xr, wr = x.astype(np.float64), wt.astype(np.float64)
+    ref = _ref(xr, wr, b.astype(np.float64), 1, transposed, True)
+    absref = _ref(np.abs(xr), np.abs(wr), np.abs(b).astype(np.float64), 1, transposed, False)
+    xd = torch.from_numpy(x).cuda()
+    got = op_conv(xd, wt, b, stride=1, transposed=transposed, relu=True, precision=precision,
+                  n_tile=1).cpu().numpy()
+    err = np.abs(got.astype(np.float64) - ref)
+    assert np.all(err <= 2e-5 * absref + 1e-6), (err.max(), (err / (absref + 1e-12)).max())
