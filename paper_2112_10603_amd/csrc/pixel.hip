@@ -25,6 +25,46 @@ __device__ inline T cvt(float v) {
 
 __device__ inline float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
 
+// 16-byte packing of activation values: N values (N a multiple of 8 for
+// bf16, of 4 for fp32) written to dst with 16-byte stores (dst 16-byte
+// aligned), and 8 values read back with one or two 16-byte loads.
+__device__ inline uint32_t pack2(float a, float b) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, (bf16)a) | ((uint32_t)__builtin_bit_cast(uint16_t, (bf16)b) << 16);
+}
+
+template <typename T, int N>
+__device__ inline void store_vals(T* dst, const float (&v)[N]) {
+  if constexpr (sizeof(T) == 2) {
+    static_assert(N % 8 == 0, "whole 16-byte chunks");
+#pragma unroll
+    for (int k = 0; k < N; k += 8)
+      *reinterpret_cast<uint4*>(dst + k) =
+          make_uint4(pack2(v[k], v[k + 1]), pack2(v[k + 2], v[k + 3]), pack2(v[k + 4], v[k + 5]),
+                     pack2(v[k + 6], v[k + 7]));
+  } else {
+    static_assert(N % 4 == 0, "whole 16-byte chunks");
+#pragma unroll
+    for (int k = 0; k < N; k += 4)
+      *reinterpret_cast<float4*>(dst + k) = make_float4(v[k], v[k + 1], v[k + 2], v[k + 3]);
+  }
+}
+
+template <typename T>
+__device__ inline void load8(const T* src, float (&v)[8]) {
+  if constexpr (sizeof(T) == 2) {
+    const uint4 u = *reinterpret_cast<const uint4*>(src);
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[2 * k] = __uint_as_float(w[k] << 16);
+      v[2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
+    }
+  } else {
+    const float4 a = *reinterpret_cast<const float4*>(src), b = *reinterpret_cast<const float4*>(src + 4);
+    v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w, v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
+  }
+}
+
 // Half-pixel-centre source coordinate for resampling n_in -> n_out.
 __device__ inline void hp_tap(int i, int n_in, int n_out, int& i0, int& i1, float& w) {
   float s = ((float)i + 0.5f) * ((float)n_in / (float)n_out) - 0.5f;
@@ -84,12 +124,8 @@ __global__ void ingest_k(const float* const* src, int H, int W, int Hp, int Wp, 
   const long HW = (long)H * W;
   const float r = s[(long)sy * W + sx], g = s[HW + (long)sy * W + sx], b = s[2 * HW + (long)sy * W + sx];
   *reinterpret_cast<float4*>(X4 + (cam * P + p) * 4) = make_float4(r, g, b, 0.f);
-  T* xa = Xa + (cam * P + p) * 8;
-  xa[0] = cvt<T>(r);
-  xa[1] = cvt<T>(g);
-  xa[2] = cvt<T>(b);
-#pragma unroll
-  for (int c = 3; c < 8; ++c) xa[c] = cvt<T>(0.f);
+  const float xv[8] = {r, g, b, 0.f, 0.f, 0.f, 0.f, 0.f};
+  store_vals<T, 8>(Xa + (cam * P + p) * 8, xv);
 }
 
 // ----------------------------------------------------- 4-channel resample
@@ -124,15 +160,8 @@ __global__ void assemble0_k(const ViewDesc* views, const CamDev* cams, int h, in
   const ViewDesc d = views[v];
   const float4 l = ld4(cams[d.cam_l].L0 + 4 * p);
   const float4 r = ld4(cams[d.cam_r].L0 + 4 * p);
-  T* o = x + ((long)v * P + p) * ld;
-  o[0] = cvt<T>(l.x);
-  o[1] = cvt<T>(l.y);
-  o[2] = cvt<T>(l.z);
-  o[3] = cvt<T>(r.x);
-  o[4] = cvt<T>(r.y);
-  o[5] = cvt<T>(r.z);
-  o[6] = cvt<T>(t_plane ? d.t : 0.f);
-  for (int c = 7; c < ld; ++c) o[c] = cvt<T>(0.f);
+  const float vals[8] = {l.x, l.y, l.z, r.x, r.y, r.z, t_plane ? d.t : 0.f, 0.f};
+  store_vals<T, 8>(x + ((long)v * P + p) * ld, vals);
 }
 
 // ---------------------------------------- stage transition s -> s+1 (Eq. 2)
@@ -168,12 +197,9 @@ __global__ void transition_k(const ViewDesc* views, const CamDev* cams, int leve
   const float4 Wl = sample4(Lc, warp_taps(xx, y, Fx, Fy, w, h));
   const float4 Wr = sample4(Rc, warp_taps(xx, y, Gx, Gy, w, h));
 
-  T* o = x + ((long)v * P + p) * ld;
-  const float vals[18] = {L.x, L.y, L.z, R.x, R.y, R.z, Wl.x, Wl.y, Wl.z, Wr.x, Wr.y, Wr.z,
-                          Mt, Fx, Fy, Gx, Gy, t_plane ? d.t : 0.f};
-#pragma unroll
-  for (int c = 0; c < 18; ++c) o[c] = cvt<T>(vals[c]);
-  for (int c = 18; c < ld; ++c) o[c] = cvt<T>(0.f);
+  const float vals[24] = {L.x, L.y, L.z, R.x, R.y, R.z, Wl.x, Wl.y, Wl.z, Wr.x, Wr.y, Wr.z,
+                          Mt, Fx, Fy, Gx, Gy, t_plane ? d.t : 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  store_vals<T, 24>(x + ((long)v * P + p) * ld, vals);
   float* f = FM + ((long)v * P + p) * 8;
   *reinterpret_cast<float4*>(f) = make_float4(Fx, Fy, Gx, Gy);
   *reinterpret_cast<float4*>(f + 4) = make_float4(Mt, 0.f, 0.f, 0.f);
@@ -204,12 +230,9 @@ __global__ void final_k(const ViewDesc* views, const CamDev* cams, const float* 
   o.z = m * Wl.z + (1.f - m) * Wr.z;
   o.w = 0.f;
   *reinterpret_cast<float4*>(I2 + ((long)v * P + p) * 4) = o;
-  T* u = x0u + ((long)v * P + p) * ld;
-  const float vals[17] = {L.x, L.y, L.z, R.x, R.y, R.z, Wl.x, Wl.y, Wl.z,
-                          Wr.x, Wr.y, Wr.z, M, F.x, F.y, F.z, F.w};
-#pragma unroll
-  for (int c = 0; c < 17; ++c) u[c] = cvt<T>(vals[c]);
-  for (int c = 17; c < ld; ++c) u[c] = cvt<T>(0.f);
+  const float vals[24] = {L.x, L.y, L.z, R.x, R.y, R.z, Wl.x, Wl.y, Wl.z, Wr.x, Wr.y, Wr.z,
+                          M, F.x, F.y, F.z, F.w, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  store_vals<T, 24>(x0u + ((long)v * P + p) * ld, vals);
 }
 
 // -------------------------------------------- flow pyramid: F/2 of 2x2 mean
@@ -259,13 +282,12 @@ __global__ void ctx_warp_k(const ViewDesc* views, const CamDev* cams, int level,
   const float ws[4] = {t.w00, t.w01, t.w10, t.w11};
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const T* s = src + (long)offs[q] * C;
+    float a[8];
+    load8<T>(src + (long)offs[q] * C, a);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) acc[i] += ws[q] * (float)s[i];
+    for (int i = 0; i < 8; ++i) acc[i] += ws[q] * a[i];
   }
-  T* o = dst + (long)v * dst_img_stride + p * dst_ld + (right ? C : 0) + c0;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) o[i] = cvt<T>(acc[i]);
+  store_vals<T, 8>(dst + (long)v * dst_img_stride + p * dst_ld + (right ? C : 0) + c0, acc);
 }
 
 // ----------------------------------------------------------- output head
@@ -396,6 +418,7 @@ hipError_t launch_resample4(const float* in, int n_img, int Hi, int Wi, float* o
 hipError_t launch_assemble0(const ViewDesc* views, int n_views, const CamDev* cams, int h, int w,
                             void* x, int ld, DType dt, int t_plane, hipStream_t s) {
   if (n_views <= 0) return hipSuccess;
+  if (ld != 8) return hipErrorInvalidValue;  // one 16-byte-aligned run of 8 channels
   if (dt == DType::F32)
     hipLaunchKernelGGL(assemble0_k<float>, grid1((long)h * w, n_views), dim3(TPB), 0, s, views, cams,
                        h, w, (float*)x, ld, t_plane);
@@ -409,6 +432,7 @@ hipError_t launch_transition(const ViewDesc* views, int n_views, const CamDev* c
                              const float* FMprev, int hp, int wp, int h, int w, void* x, int ld,
                              float* FM, DType dt, int t_plane, hipStream_t s) {
   if (n_views <= 0) return hipSuccess;
+  if (ld != 24) return hipErrorInvalidValue;  // 18 channels padded to 24 (16-byte runs)
   if (dt == DType::F32)
     hipLaunchKernelGGL(transition_k<float>, grid1((long)h * w, n_views), dim3(TPB), 0, s, views, cams,
                        level, FMprev, hp, wp, h, w, (float*)x, ld, FM, t_plane);
@@ -421,6 +445,7 @@ hipError_t launch_transition(const ViewDesc* views, int n_views, const CamDev* c
 hipError_t launch_final(const ViewDesc* views, int n_views, const CamDev* cams, const float* FM,
                         int h, int w, float* I2, void* x0u, int ld, DType dt, hipStream_t s) {
   if (n_views <= 0) return hipSuccess;
+  if (ld != 24) return hipErrorInvalidValue;  // 17 channels padded to 24 (16-byte runs)
   if (dt == DType::F32)
     hipLaunchKernelGGL(final_k<float>, grid1((long)h * w, n_views), dim3(TPB), 0, s, views, cams, FM, h,
                        w, I2, (float*)x0u, ld);
@@ -442,7 +467,10 @@ hipError_t launch_ctx_warp(const ViewDesc* views, int n_views, const CamDev* cam
                            const float* flow, int h, int w, void* dst, int dst_ld,
                            long dst_img_stride, DType dt, hipStream_t s) {
   if (n_views <= 0) return hipSuccess;
-  if (C % 8 != 0) return hipErrorInvalidValue;
+  // 8-channel groups as 16-byte loads and stores
+  if (C % 8 != 0 || dst_ld % 8 != 0 || dst_img_stride % 8 != 0 ||
+      reinterpret_cast<uintptr_t>(dst) % 16 != 0)
+    return hipErrorInvalidValue;
   const long n = (long)h * w * (C / 4);
   if (dt == DType::F32)
     hipLaunchKernelGGL(ctx_warp_k<float>, grid1(n, n_views), dim3(TPB), 0, s, views, cams, level, C,
