@@ -270,12 +270,15 @@ def _enc(W, k, z, taps=None):
     return conv_layer(W, f"unet.enc{2 * k + 2}", z, taps=taps)
 
 
-def vinet_forward(xl, xr, t, W, taps: dict | None = None):
+def vinet_forward(xl, xr, t, W, taps: dict | None = None, refine: bool = True):
     """Synthesise the view at phase ``t`` between ``xl`` and ``xr``.
 
     ``xl``, ``xr``: [3, H, W] in [0, 1] (any float type; computed in float64).
     ``W``: the dict from ``load_weights``. Returns [3, H, W] float64.
     If ``taps`` is a dict, intermediate tensors are stored in it.
+    ``refine=False`` returns the flow-and-mask blend of Eq. 1 alone (the
+    paper's "w/o Refine" variant of its ablation, Table 1), cropped: no
+    context features, no U-Net, no residual.
     """
     xl = np.asarray(xl, dtype=np.float64)
     xr = np.asarray(xr, dtype=np.float64)
@@ -323,6 +326,8 @@ def vinet_forward(xl, xr, t, W, taps: dict | None = None):
     I2 = blend(Wl, Wr, M)
     if taps is not None:
         taps["I2"] = I2
+    if not refine:
+        return I2[:, :H, :Wd]
 
     # context features, warped to the middle view by the flow pyramid
     cl = context_net(W, Xl, taps)
@@ -350,3 +355,22 @@ def vinet_forward(xl, xr, t, W, taps: dict | None = None):
                      "u1": u1, "u2": u2, "u3": u3, "u4": u4, "r": r,
                      "ctx_l": cl, "ctx_r": cr, "wc": wc, "x0": x0})
     return out[:, :H, :Wd]
+
+
+def vinet_recursive(xl, xr, levels, W, refine: bool = True):
+    """Dense views by recursive midpoints (the paper's dense-view scheme,
+    section 4, Fig. 6): level 1 synthesises the middle view of (xl, xr);
+    each further level synthesises the middle view of every adjacent pair
+    of the views so far. ``levels`` = n gives the 2^n - 1 views at
+    t = k / 2^n, k = 1 .. 2^n - 1, returned in order of k as a list of
+    [3, H, W] float64 arrays. Every synthesis is ``vinet_forward`` at t = 1/2.
+    """
+    if levels < 1:
+        raise ValueError("levels must be >= 1")
+    n = 1 << levels
+    views = {0: np.asarray(xl, dtype=np.float64), n: np.asarray(xr, dtype=np.float64)}
+    for level in range(1, levels + 1):
+        step = n >> level
+        for k in range(step, n, 2 * step):
+            views[k] = vinet_forward(views[k - step], views[k + step], 0.5, W, refine=refine)
+    return [views[k] for k in range(1, n)]

@@ -142,10 +142,17 @@ def structured_weights(
 
     ``kind="const_flow"``: as ``zero_heads``, but VIBlock 0's last bias is
     (0.5, 0, -0.5, 0, 0).
+
+    ``kind="zero_refine"``: only the output head is zero (random flow and
+    mask), so the refinement residual is exactly 0.
     """
     W = make_weights(seed, base_width, t_plane)
-    if kind not in ("zero_heads", "const_flow"):
+    if kind not in ("zero_heads", "const_flow", "zero_refine"):
         raise ValueError(kind)
+    if kind == "zero_refine":
+        w, b = W["unet.head"]
+        W["unet.head"] = (np.zeros_like(w), np.zeros_like(b))
+        return W
     for name in ["vib0.convT2", "vib1.convT2", "vib2.convT2", "unet.head"]:
         w, b = W[name]
         W[name] = (np.zeros_like(w), np.zeros_like(b))

@@ -129,3 +129,68 @@ def test_weights_roundtrip(random_weights_file):
         np.testing.assert_array_equal(W["layers"][name][3], b.astype(np.float64))
     head = open(random_weights_file, "rb").read(4096)
     assert re.search(rb"sha256 [0-9a-f]{64}", head)
+
+
+def test_blend_only_closed_forms(weights_dir):
+    """The "w/o Refine" output (the Eq. 1 blend alone): zero heads give the
+    plain average; constant-flow heads give the true middle view T(x + 2)."""
+    pz = write_weights_file(str(weights_dir / "zero_b.ffvw"), seed=3, kind="zero_heads")
+    xl, xr = scenes.random_pair(7, 40, 72)
+    out = O.vinet_forward(xl.numpy(), xr.numpy(), 0.7, O.load_weights(pz), refine=False)
+    want = 0.5 * (xl.numpy().astype(np.float64) + xr.numpy().astype(np.float64))
+    np.testing.assert_allclose(out, want, rtol=0, atol=1e-15)
+    pc = write_weights_file(str(weights_dir / "cflow_b.ffvw"), seed=0, kind="const_flow")
+    xl, xr = scenes.small_pair()
+    out = O.vinet_forward(xl.numpy(), xr.numpy(), 0.5, O.load_weights(pc), refine=False)
+    W_ = xl.shape[2]
+    np.testing.assert_array_equal(out[:, :, 2:W_ - 2], xl.numpy()[:, :, 4:].astype(np.float64))
+
+
+def test_blend_only_equals_full_net_without_residual(weights_dir):
+    """Random flow/mask weights with a zero output head: the residual
+    2*sigma(0) - 1 is exactly 0 and the blend lies in [0, 1], so the full
+    network's output equals the blend-only output up to the rounding of
+    (I2 + 1) - 1, i.e. within one ulp of 1.0."""
+    p = write_weights_file(str(weights_dir / "zref.ffvw"), seed=5, kind="zero_refine")
+    W = O.load_weights(p)
+    xl, xr = scenes.random_pair(17, 36, 52, d_max=5.0)
+    full = O.vinet_forward(xl.numpy(), xr.numpy(), 0.4, W)
+    blend = O.vinet_forward(xl.numpy(), xr.numpy(), 0.4, W, refine=False)
+    assert blend.shape == (3, 36, 52)
+    np.testing.assert_allclose(full, blend, rtol=0, atol=2.3e-16)
+    # and a random output head does change it
+    W2 = O.load_weights(write_weights_file(str(weights_dir / "rref.ffvw"), seed=5))
+    assert np.abs(O.vinet_forward(xl.numpy(), xr.numpy(), 0.4, W2) - blend).max() > 1e-3
+
+
+@pytest.mark.parametrize("levels", [1, 2, 3])
+def test_recursive_midpoints_zero_heads_are_linear(weights_dir, levels):
+    """Dense views by recursive midpoints: 2^n - 1 views (paper, section 4:
+    n levels give 2^n - 1 virtual views). With zero heads every synthesis is
+    the average of its two inputs, so the view at t = k/2^n is exactly the
+    linear blend (1 - t) X_l + t X_r."""
+    p = write_weights_file(str(weights_dir / "zero_r.ffvw"), seed=3, kind="zero_heads")
+    W = O.load_weights(p)
+    xl, xr = scenes.random_pair(9, 32, 48)
+    a, b = xl.numpy().astype(np.float64), xr.numpy().astype(np.float64)
+    views = O.vinet_recursive(xl.numpy(), xr.numpy(), levels, W)
+    n = 1 << levels
+    assert len(views) == n - 1
+    for k, v in enumerate(views, start=1):
+        t = k / n
+        np.testing.assert_allclose(v, (1 - t) * a + t * b, rtol=0, atol=1e-14)
+
+
+def test_recursive_wiring(random_weights_file):
+    """Level 1 is the t = 1/2 synthesis; level 2 synthesises the middles of
+    (X_l, V_1/2) and (V_1/2, X_r)."""
+    W = O.load_weights(random_weights_file)
+    xl, xr = scenes.random_pair(19, 32, 32, d_max=4.0)
+    a, b = xl.numpy(), xr.numpy()
+    v = O.vinet_recursive(a, b, 2, W)
+    mid = O.vinet_forward(a, b, 0.5, W)
+    np.testing.assert_array_equal(v[1], mid)
+    np.testing.assert_array_equal(v[0], O.vinet_forward(a, mid, 0.5, W))
+    np.testing.assert_array_equal(v[2], O.vinet_forward(mid, b, 0.5, W))
+    with pytest.raises(ValueError):
+        O.vinet_recursive(a, b, 0, W)
