@@ -215,6 +215,52 @@ def fp8_4k_leg(wpath, dev, reps=3, with_oracle=True, crops_per_pair=4):
     return res
 
 
+def next_leg(wpath, dev, reps=5):
+    """The paper's two other inference modes, timed on the GPU beside the
+    direct t-plane path (BF16, batch of one pair, inputs resident):
+    * w/o Refine (the Eq. 1 blend alone; Table 1) against the full network,
+      one 1280x720 pair at t = 1/2;
+    * recursive midpoints (section 4) against direct phases for the dyadic
+      t in {1/4, 1/2, 3/4}, one 1080p pair: two dependent levels (1 + 2
+      syntheses) versus one call with three phases, and how far the two
+      results lie apart (PSNR of one against the other; both are valid
+      views of different methods)."""
+    import numpy as np
+    import torch
+
+    from paper_2112_10603_amd import Net
+    from synth import scenes
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return 1000.0 * (time.perf_counter() - a) / reps
+
+    net = Net(wpath, "bf16", 0, workspace_bytes=32 << 30)
+    hd = scenes.camera_arc(50, 720, 1280, 2, 1024, (8.0, 64.0), 48.0, 0.01, device=dev)
+    p720 = [(hd[0], hd[1])]
+    o1 = torch.empty((1, 1, 3, 720, 1280), device=dev)
+    full_ms = timed(lambda: net.interpolate(p720, [0.5], o1))
+    blend_ms = timed(lambda: net.interpolate_blend(p720, [0.5], o1))
+    fhd = scenes.camera_arc(2, 1080, 1920, 2, 1024, (8.0, 64.0), 48.0, 0.01, device=dev)
+    p1080 = [(fhd[0], fhd[1])]
+    od = torch.empty((1, 3, 3, 1080, 1920), device=dev)
+    orc = torch.empty((1, 3, 3, 1080, 1920), device=dev)
+    direct_ms = timed(lambda: net.interpolate(p1080, [0.25, 0.5, 0.75], od))
+    rec_ms = timed(lambda: net.interpolate_recursive(p1080, 2, orc))
+    mse = torch.mean((od.double() - orc.double()) ** 2).item()
+    net.close()
+    return {"w/o_refine_720p": {"full_ms": round(full_ms, 3), "blend_only_ms": round(blend_ms, 3),
+                                "paper_table1_ms_rtx_a6000": {"full": 12.85, "w/o_refine": 6.27}},
+            "recursive_vs_direct_1080p_dyadic": {
+                "direct_3_phases_ms": round(direct_ms, 3), "recursive_2_levels_ms": round(rec_ms, 3),
+                "psnr_db_between_methods": round(10 * math.log10(1.0 / mse), 2) if mse > 0 else None}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +276,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 4K leg")
     ap.add_argument("--no-tune", action="store_true", help="skip conv tile autotuning")
+    ap.add_argument("--no-next", action="store_true", help="skip the w/o-refine and recursive leg")
     ap.add_argument("--tune-file", default=None,
                     help="load the conv tuning table from this file if it exists, else tune and "
                          "save it there")
@@ -376,6 +423,11 @@ def main():
         fp8 = fp8_4k_leg(wpath, dev, with_oracle=not args.no_oracle)
         print(f"[bench] fp8 4K: {fp8['views_per_s']} views/s", file=sys.stderr, flush=True)
 
+    modes = None
+    if not args.no_next:
+        modes = next_leg(wpath, dev)
+        print(f"[bench] modes: {modes}", file=sys.stderr, flush=True)
+
     cpu = None
     psnr = None
     if not args.no_oracle:
@@ -424,6 +476,7 @@ def main():
         "fp32_plain": fp32,
         "serving": serving,
         "fp8_4k": fp8,
+        "inference_modes": modes,
         "bf16_vs_fp32": None if fp32 is None else round(value / fp32["views_per_s"], 2),
         "conv_mfma_util": round(conv_flops / (conv_ms * 1e-3) / 1e12 / PEAK_BF16_TFLOPS, 4)
         if conv_ms > 0 else None,

@@ -109,6 +109,28 @@ ffv_status ffv_interpolate(ffv_net* net, const ffv_pair* views, int32_t n_pairs,
                            const float* t, int32_t n_t, float* out);
 
 /*
+ * The flow-and-mask blend alone (Eq. 1: I = sigma(M) W_l + (1 - sigma(M)) W_r
+ * with the coarse-to-fine flow and mask of Eq. 2): the paper's "w/o Refine"
+ * variant of its ablation (Table 1), with no context features, U-Net or
+ * residual. Arguments, layout and errors as ffv_interpolate.
+ */
+ffv_status ffv_interpolate_blend(ffv_net* net, const ffv_pair* views, int32_t n_pairs,
+                                 const float* t, int32_t n_t, float* out);
+
+/*
+ * Dense views by recursive midpoints (the paper's dense-view scheme,
+ * section 4, Fig. 6): level 1 synthesises the middle view of each pair, and
+ * every further level the middle view of each adjacent pair of the views so
+ * far, all at t = 1/2. levels = n in [1, 10] gives 2^n - 1 views per pair:
+ *   out: DEVICE float32 [n_pairs][2^n - 1][3][H][W], view k-1 at t = k/2^n.
+ * One batched launch sequence per level (level l holds n_pairs * 2^(l-1)
+ * views); a view's two neighbours are read back from `out`. Errors as
+ * ffv_interpolate, plus FFV_ERR_ARG for levels outside [1, 10].
+ */
+ffv_status ffv_interpolate_recursive(ffv_net* net, const ffv_pair* views, int32_t n_pairs,
+                                     int32_t levels, float* out);
+
+/*
  * Conv tile autotuning (the conv kernel is instantiated for 256-pixel M tiles
  * with 256/128/64/32-channel N tiles; the 256 pixels form a tile_w-wide 2-D
  * block). Runs the call exactly as ffv_interpolate does (same arguments, same

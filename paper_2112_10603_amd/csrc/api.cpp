@@ -138,6 +138,46 @@ ffv_status ffv_load_tuning(ffv_net* net, const char* path, int32_t* n_loaded) {
   }
 }
 
+ffv_status ffv_interpolate_blend(ffv_net* net, const ffv_pair* views, int32_t n_pairs,
+                                 const float* t, int32_t n_t, float* out) {
+  const ffv_status c = check_call(net, views, n_pairs, t, n_t, out);
+  if (c != FFV_OK) return c;
+  try {
+    std::vector<const float*> l(n_pairs), r(n_pairs);
+    for (int i = 0; i < n_pairs; ++i) {
+      l[i] = views[i].left;
+      r[i] = views[i].right;
+    }
+    return from(net->net.interpolate_blend(l.data(), r.data(), n_pairs, views[0].height,
+                                           views[0].width, t, n_t, out));
+  } catch (const std::bad_alloc&) {
+    return fail(FFV_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(FFV_ERR_DEVICE, e.what());
+  }
+}
+
+ffv_status ffv_interpolate_recursive(ffv_net* net, const ffv_pair* views, int32_t n_pairs,
+                                     int32_t levels, float* out) {
+  if (levels < 1 || levels > 10) return fail(FFV_ERR_ARG, "levels must lie in [1, 10]");
+  const float half = 0.5f;
+  const ffv_status c = check_call(net, views, n_pairs, &half, 1, out);
+  if (c != FFV_OK) return c;
+  try {
+    std::vector<const float*> l(n_pairs), r(n_pairs);
+    for (int i = 0; i < n_pairs; ++i) {
+      l[i] = views[i].left;
+      r[i] = views[i].right;
+    }
+    return from(net->net.interpolate_recursive(l.data(), r.data(), n_pairs, views[0].height,
+                                               views[0].width, levels, out));
+  } catch (const std::bad_alloc&) {
+    return fail(FFV_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(FFV_ERR_DEVICE, e.what());
+  }
+}
+
 ffv_status ffv_interpolate(ffv_net* net, const ffv_pair* views, int32_t n_pairs, const float* t,
                            int32_t n_t, float* out) {
   const ffv_status c = check_call(net, views, n_pairs, t, n_t, out);

@@ -112,6 +112,10 @@ hipError_t launch_flow_down(const float* in, int in_ld, int n_img, int h, int w,
 hipError_t launch_ctx_warp(const ViewDesc* views, int n_views, const CamDev* cams, int level, int C,
                            const float* flow, int h, int w, void* dst, int dst_ld,
                            long dst_img_stride, DType dt, hipStream_t s);
+// Blend-only output: I2 (padded NHWC, 4 floats) cropped to planar [3][H][W]
+// at each view's out pointer.
+hipError_t launch_blend_out(const float* I2, const ViewDesc* views, int n_img, int Hp, int Wp, int H,
+                            int W, hipStream_t s);
 hipError_t launch_head(const void* u4, int ld, int C, const float* w, const float* b,
                        const float* I2, const ViewDesc* views, int n_img, int Hp, int Wp, int H,
                        int W, DType dt, hipStream_t s);

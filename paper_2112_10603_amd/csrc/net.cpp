@@ -639,7 +639,7 @@ Status Net::conv(const Exec& x, const Layer& L, const void* in, int in_ld, long 
 }
 
 Status Net::build_cameras(const Exec& x, const Geo& g, const float* const* src_dev, int n_cam,
-                          char* const* blocks, char* ctmp) {
+                          char* const* blocks, char* ctmp, bool context) {
   if (n_cam <= 0) return Status::ok();
   const CamPlan c = cam_plan(g);
   const int B = base_width_;
@@ -668,6 +668,7 @@ Status Net::build_cameras(const Exec& x, const Geo& g, const float* const* src_d
     prof_end(x, "pixel", (double)g.H * g.W * 12 + P * (16.0 + 8 * e) + 2 * P * 16.0 +
                              (P / 16 + P / 4) * 16.0);
   }
+  if (!context) return Status::ok();
   // ContextNet batched over the cameras: image stride = camera block stride
   const int cw[4] = {B / 2, B, 2 * B, 4 * B};
   const char* src = b0 + c.Xa;
@@ -692,7 +693,7 @@ Status Net::build_cameras(const Exec& x, const Geo& g, const float* const* src_d
 }
 
 Status Net::run_views(const Exec& x, const ViewPlan& p, const CamDev* cams,
-                      const ViewDesc* views_in, int nv, bool views_on_device) {
+                      const ViewDesc* views_in, int nv, bool views_on_device, bool refine) {
   const Geo& g = p.g;
   const long P = g.P;
   const int B = base_width_;
@@ -758,6 +759,14 @@ Status Net::run_views(const Exec& x, const ViewPlan& p, const CamDev* cams,
                              (float*)x.at(p.I2), x.at(p.x0u), 24, dt_, x.s),
                 "final"));
   prof_end(x, "pixel", (double)nv * P * (20.0 + 16 * 4 + 16 + 24 * e));
+
+  if (!refine) {  // the blend is the output
+    prof_begin(x);
+    FFV_TRY(check(launch_blend_out((const float*)x.at(p.I2), views, nv, g.Hp, g.Wp, g.H, g.W, x.s),
+                  "blend out"));
+    prof_end(x, "pixel", (double)nv * (16.0 * g.H * g.W + 12.0 * g.H * g.W));
+    return Status::ok();
+  }
 
   // flow pyramid and context warps
   {
@@ -843,8 +852,46 @@ Status Net::interpolate(const float* const* left, const float* const* right, int
   return interpolate_locked(left, right, n_pairs, H, W, t, n_t, out);
 }
 
+Status Net::interpolate_blend(const float* const* left, const float* const* right, int n_pairs, int H,
+                              int W, const float* t, int n_t, float* out) {
+  std::lock_guard<std::mutex> lk(call_mu_);
+  std::vector<float*> outs((size_t)n_pairs * n_t);
+  for (size_t v = 0; v < outs.size(); ++v) outs[v] = out + v * 3 * (size_t)H * W;
+  return run_call(left, right, n_pairs, H, W, t, n_t, outs.data(), false);
+}
+
+Status Net::interpolate_recursive(const float* const* left, const float* const* right, int n_pairs,
+                                  int H, int W, int levels, float* out) {
+  if (levels < 1 || levels > 10) return Status::err(-1, "levels must lie in [1, 10]");
+  std::lock_guard<std::mutex> lk(call_mu_);
+  const int n = 1 << levels;
+  const size_t img = 3 * (size_t)H * W;
+  auto view = [&](int i, int k) -> float* { return out + ((size_t)i * (n - 1) + (k - 1)) * img; };
+  const float half = 0.5f;
+  for (int level = 1; level <= levels; ++level) {
+    const int step = n >> level;
+    std::vector<const float*> l, r;
+    std::vector<float*> o;
+    for (int i = 0; i < n_pairs; ++i)
+      for (int k = step; k < n; k += 2 * step) {
+        l.push_back(k - step == 0 ? left[i] : view(i, k - step));
+        r.push_back(k + step == n ? right[i] : view(i, k + step));
+        o.push_back(view(i, k));
+      }
+    FFV_TRY(run_call(l.data(), r.data(), (int)l.size(), H, W, &half, 1, o.data(), true));
+  }
+  return Status::ok();
+}
+
 Status Net::interpolate_locked(const float* const* left, const float* const* right, int n_pairs,
                                int H, int W, const float* t, int n_t, float* out) {
+  std::vector<float*> outs((size_t)n_pairs * n_t);
+  for (size_t v = 0; v < outs.size(); ++v) outs[v] = out + v * 3 * (size_t)H * W;
+  return run_call(left, right, n_pairs, H, W, t, n_t, outs.data(), true);
+}
+
+Status Net::run_call(const float* const* left, const float* const* right, int n_pairs, int H, int W,
+                     const float* t, int n_t, float* const* outs, bool refine) {
   if (!ready() && !calibrating_) return Status::err(-7, "FP8 net needs ffv_calibrate first");
   FFV_TRY(check(hipSetDevice(device_), "hipSetDevice"));
   const Geo g = Geo::of(H, W);
@@ -909,7 +956,7 @@ Status Net::interpolate_locked(const float* const* left, const float* const* rig
       d.cam_l = li[i];
       d.cam_r = ri[i];
       d.t = t[j];
-      d.out = out + ((size_t)i * n_t + j) * 3 * (size_t)H * W;
+      d.out = outs[(size_t)i * n_t + j];
     }
   // Graph replay needs every per-call value in device tables: the camera
   // and image tables above, and here all views' descriptors.
@@ -924,16 +971,17 @@ Status Net::interpolate_locked(const float* const* left, const float* const* rig
   Exec xv = x;
   xv.ws = base + fixed;
   auto launch_all = [&]() -> Status {
-    FFV_TRY(build_cameras(x, g, src_tab, n_cam, blocks.data(), ctmp));
+    FFV_TRY(build_cameras(x, g, src_tab, n_cam, blocks.data(), ctmp, refine));
     for (int v0 = 0; v0 < n_view_total; v0 += chunk) {
       const int nv = std::min(chunk, n_view_total - v0);
-      FFV_TRY(run_views(xv, vp, cam_tab, use_graph ? view_tab + v0 : vd.data() + v0, nv, use_graph));
+      FFV_TRY(run_views(xv, vp, cam_tab, use_graph ? view_tab + v0 : vd.data() + v0, nv, use_graph,
+                        refine));
     }
     return Status::ok();
   };
   const GraphEntry* ran = nullptr;
   if (use_graph) {
-    const GraphKey key{H, W, n_cam, n_view_total, chunk, ws_, vib_fp8(), profiling_};
+    const GraphKey key{H, W, n_cam, n_view_total, chunk, ws_, vib_fp8(), profiling_, refine};
     auto it = graph_cache_.find(key);
     if (it == graph_cache_.end()) {
       pending_.clear();

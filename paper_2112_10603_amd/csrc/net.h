@@ -118,6 +118,15 @@ class Net {
               size_t workspace_cap);
   Status interpolate(const float* const* left, const float* const* right, int n_pairs, int H, int W,
                      const float* t, int n_t, float* out);
+  // The Eq. 1 blend alone (no context features, U-Net or residual: the
+  // paper's "w/o Refine" variant), same arguments and layout.
+  Status interpolate_blend(const float* const* left, const float* const* right, int n_pairs, int H,
+                           int W, const float* t, int n_t, float* out);
+  // Dense views by recursive midpoints: `levels` = n gives, per pair, the
+  // 2^n - 1 views at t = k/2^n (k = 1 .. 2^n - 1) in out[pair][k - 1], each
+  // the t = 1/2 synthesis of its two neighbours; one batched call per level.
+  Status interpolate_recursive(const float* const* left, const float* const* right, int n_pairs,
+                               int H, int W, int levels, float* out);
   Status debug_tap(const std::string& name, float* dst, size_t cap, int dims[3]);
   // FP8 nets: run one view in bf16, record the VIBlock activations' per-channel
   // ranges, then quantise those layers' weights (needed before use).
@@ -151,18 +160,22 @@ class Net {
   // planar [3][H][W] images; camera i's block starts at blocks[i] (host
   // array of device pointers). ctmp is scratch of n_cam * cp.ctmp bytes.
   Status build_cameras(const Exec& x, const Geo& g, const float* const* src_dev, int n_cam,
-                       char* const* blocks, char* ctmp);
+                       char* const* blocks, char* ctmp, bool context = true);
   // Run nv views. views_on_device: `views` is a device table that stays
   // valid until the work completes; otherwise a host array copied to the
   // plan's view slot on the stream.
   Status run_views(const Exec& x, const ViewPlan& p, const CamDev* cams_dev, const ViewDesc* views,
-                   int nv, bool views_on_device = false);
+                   int nv, bool views_on_device = false, bool refine = true);
   CamDev cam_dev(const Geo& g, char* block) const;
   Status check(hipError_t e, const char* what) const;
 
  private:
   Status interpolate_locked(const float* const* left, const float* const* right, int n_pairs, int H,
                             int W, const float* t, int n_t, float* out);
+  // One batched call: view i*n_t + j of pair i at t[j] is written to
+  // outs[i*n_t + j] (planar [3][H][W] device pointers).
+  Status run_call(const float* const* left, const float* const* right, int n_pairs, int H, int W,
+                  const float* t, int n_t, float* const* outs, bool refine);
   Status ensure_workspace(size_t bytes);
   void drop_graphs();
   Status conv(const Exec& x, const Layer& L, const void* in, int in_ld, long in_img_stride, int Hi,
@@ -210,10 +223,10 @@ class Net {
   struct GraphKey {
     int H, W, n_cam, n_view, chunk;
     const void* ws;
-    bool fp8, prof;
+    bool fp8, prof, refine;
     bool operator<(const GraphKey& o) const {
-      return std::tie(H, W, n_cam, n_view, chunk, ws, fp8, prof) <
-             std::tie(o.H, o.W, o.n_cam, o.n_view, o.chunk, o.ws, o.fp8, o.prof);
+      return std::tie(H, W, n_cam, n_view, chunk, ws, fp8, prof, refine) <
+             std::tie(o.H, o.W, o.n_cam, o.n_view, o.chunk, o.ws, o.fp8, o.prof, o.refine);
     }
   };
   struct GraphEntry {

@@ -235,6 +235,21 @@ __global__ void final_k(const ViewDesc* views, const CamDev* cams, const float* 
   store_vals<T, 24>(x0u + ((long)v * P + p) * ld, vals);
 }
 
+// ------------------------------- blend-only output (no refinement, Table 1)
+// out = I2, cropped to H x W and written planar [3][H][W].
+__global__ void blend_out_k(const float* I2, const ViewDesc* views, int Hp, int Wp, int H, int W) {
+  const int v = blockIdx.y;
+  const long p = (long)blockIdx.x * TPB + threadIdx.x;
+  if (p >= (long)H * W) return;
+  const int y = (int)(p / W), x = (int)(p % W);
+  const float4 b = ld4(I2 + ((long)v * Hp * Wp + (long)y * Wp + x) * 4);
+  const long HW = (long)H * W;
+  float* o = views[v].out;
+  o[p] = b.x;
+  o[HW + p] = b.y;
+  o[2 * HW + p] = b.z;
+}
+
 // -------------------------------------------- flow pyramid: F/2 of 2x2 mean
 __global__ void flow_down_k(const float* in, int in_ld, int h, int w, float* out) {
   const int img = blockIdx.y;
@@ -506,6 +521,13 @@ hipError_t launch_head(const void* u4, int ld, int C, const float* w, const floa
     case 56: go(std::integral_constant<int, 56>{}); break;
     default: go(std::integral_constant<int, 64>{}); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_blend_out(const float* I2, const ViewDesc* views, int n_img, int Hp, int Wp, int H,
+                            int W, hipStream_t s) {
+  if (n_img <= 0) return hipSuccess;
+  hipLaunchKernelGGL(blend_out_k, grid1((long)H * W, n_img), dim3(TPB), 0, s, I2, views, Hp, Wp, H, W);
   return hipGetLastError();
 }
 

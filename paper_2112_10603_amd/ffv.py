@@ -27,7 +27,8 @@ STATUS = {0: "FFV_OK", 1: "FFV_PENDING", -1: "FFV_ERR_ARG", -2: "FFV_ERR_OOM",
 EXPORTS = ["ffv_default_opts", "ffv_create_net", "ffv_destroy_net", "ffv_interpolate",
            "ffv_last_error", "ffv_calibrate", "ffv_register_camera", "ffv_submit", "ffv_poll", "ffv_serving_stats",
            "ffv_debug_tap", "ffv_set_debug", "ffv_set_profiling", "ffv_kernel_stats", "ffv_op_conv",
-           "ffv_autotune", "ffv_save_tuning", "ffv_load_tuning"]
+           "ffv_autotune", "ffv_save_tuning", "ffv_load_tuning", "ffv_interpolate_blend",
+           "ffv_interpolate_recursive"]
 
 
 class FfvError(RuntimeError):
@@ -97,6 +98,11 @@ def lib() -> ctypes.CDLL:
     L.ffv_autotune.argtypes = [c_void, ctypes.POINTER(ffv_pair), c_int, ctypes.POINTER(c_f), c_int,
                                c_void, ctypes.POINTER(c_int)]
     L.ffv_autotune.restype = c_int
+    L.ffv_interpolate_blend.argtypes = [c_void, ctypes.POINTER(ffv_pair), c_int, ctypes.POINTER(c_f),
+                                        c_int, c_void]
+    L.ffv_interpolate_blend.restype = c_int
+    L.ffv_interpolate_recursive.argtypes = [c_void, ctypes.POINTER(ffv_pair), c_int, c_int, c_void]
+    L.ffv_interpolate_recursive.restype = c_int
     L.ffv_save_tuning.argtypes = [c_void, ctypes.c_char_p]
     L.ffv_save_tuning.restype = c_int
     L.ffv_load_tuning.argtypes = [c_void, ctypes.c_char_p, ctypes.POINTER(c_int)]
@@ -174,6 +180,20 @@ class Net:
         ``ts``: phases in [0, 1]. Returns [n_pairs, n_t, 3, H, W] float32."""
         arr, tarr, out = self._call_args(pairs, ts, out)
         _check(lib().ffv_interpolate(self._h, arr, len(arr), tarr, len(tarr), out.data_ptr()))
+        return out
+
+    def interpolate_blend(self, pairs, ts, out: torch.Tensor | None = None) -> torch.Tensor:
+        """The Eq. 1 blend alone (no refinement), shaped as ``interpolate``."""
+        arr, tarr, out = self._call_args(pairs, ts, out)
+        _check(lib().ffv_interpolate_blend(self._h, arr, len(arr), tarr, len(tarr), out.data_ptr()))
+        return out
+
+    def interpolate_recursive(self, pairs, levels: int, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Recursive midpoints: [n_pairs, 2^levels - 1, 3, H, W], view k-1 at
+        t = k / 2^levels."""
+        n_views = (1 << levels) - 1
+        arr, _, out = self._call_args(pairs, [0.5] * n_views, out)
+        _check(lib().ffv_interpolate_recursive(self._h, arr, len(arr), levels, out.data_ptr()))
         return out
 
     def autotune(self, pairs, ts, out: torch.Tensor | None = None) -> int:
