@@ -277,6 +277,8 @@ def main():
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 4K leg")
     ap.add_argument("--no-tune", action="store_true", help="skip conv tile autotuning")
     ap.add_argument("--no-next", action="store_true", help="skip the w/o-refine and recursive leg")
+    ap.add_argument("--fp8-only", action="store_true",
+                    help="run only the FP8 4K leg (no JSON line; for profiling)")
     ap.add_argument("--tune-file", default=None,
                     help="load the conv tuning table from this file if it exists, else tune and "
                          "save it there")
@@ -297,6 +299,11 @@ def main():
     from synth.weights import write_weights_file
 
     dev = torch.device("cuda:0")
+    if args.fp8_only:
+        td = tempfile.mkdtemp()
+        wpath = write_weights_file(os.path.join(td, "w.ffvw"), seed=0)
+        print(json.dumps(fp8_4k_leg(wpath, dev, with_oracle=False)), flush=True)
+        return
     if args.copy_calib:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -373,6 +380,31 @@ def main():
     conv_flops = sum(stats[k]["work"] for k in ("conv256", "conv", "convT"))
     breakdown = {k: {"launches": v["launches"], "ms_per_step": round(v["ms"] / args.steps, 3)}
                  for k, v in stats.items()}
+
+    # cluster frame of the middle camera from this step's outputs (the
+    # Multiview Organizer): its real view between 16 views on either side
+    stitch = None
+    if len(pairs) >= 2 and len(ts) == 16 and H % 4 == 0 and W % 4 == 0:
+        from paper_2112_10603_amd import stitch_cluster
+        c = len(pairs) // 2 + 1 if len(pairs) > 2 else 1
+        left = [out[c - 1, k] for k in range(16)]    # far (t ~ 0) to near the camera
+        right = [out[c, k] for k in range(16)]       # near the camera outwards
+        frame = torch.empty((3, H, 3 * W), device=dev)
+        cs = torch.cuda.current_stream(dev)
+        stitch_cluster(arc[c], left, right, frame)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record(cs)
+        for _ in range(reps):
+            stitch_cluster(arc[c], left, right, frame)
+        e1.record(cs)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        nbytes = 33 * 3 * H * W * 4 + 3 * H * 3 * W * 4
+        stitch = {"ms_per_cluster_frame": round(ms, 4), "frame": f"3x{H}x{3 * W} fp32, 33 views",
+                  "hbm_gbs_algorithmic": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                  "paper_table2_adaptive_stitch_ms": 1.27}
+        del frame
 
     # one BF16 view kept for the PSNR check: pair 0, t = 8/17
     j_ref = len(ts) // 2 - 1
@@ -477,6 +509,7 @@ def main():
         "serving": serving,
         "fp8_4k": fp8,
         "inference_modes": modes,
+        "cluster_stitch": stitch,
         "bf16_vs_fp32": None if fp32 is None else round(value / fp32["views_per_s"], 2),
         "conv_mfma_util": round(conv_flops / (conv_ms * 1e-3) / 1e12 / PEAK_BF16_TFLOPS, 4)
         if conv_ms > 0 else None,

@@ -257,6 +257,25 @@ ffv_status ffv_kernel_stats(ffv_net* net, const char* name, int64_t* launches, d
                             double* work);
 
 /*
+ * Multi-view cluster frame (the Multiview Organizer of section 3.2; the
+ * supplement's clusters of 16 views per side, 33 views in all): the real
+ * view of a camera at full resolution between two blocks of its
+ * neighbouring views, each downscaled by g = sqrt(n_per_side) in both
+ * directions (g x g box mean) and tiled g x g in raster order, so each side
+ * fills one H x W block:
+ *   out[3][H][3W] = [left block | real view | right block]
+ * real_view: DEVICE planar [3][H][W]; left, right: HOST arrays of
+ * n_per_side DEVICE planar [3][H][W] views (left: far to near, right: near
+ * to far); out: DEVICE planar [3][H][3W]. n_per_side in {1, 4, 16, 64};
+ * H and W multiples of g; views 16-byte aligned when g = 4. Enqueued on
+ * `stream` (NULL = default stream), asynchronous. Errors: FFV_ERR_ARG,
+ * FFV_ERR_DEVICE.
+ */
+ffv_status ffv_stitch_cluster(const float* real_view, const float* const* left,
+                              const float* const* right, int32_t n_per_side, int32_t height,
+                              int32_t width, float* out, void* stream);
+
+/*
  * One convolution layer through the library's implicit-GEMM kernel (kernel
  * unit tests). 3x3 conv, padding 1, stride 1 or 2 (transposed = 0), or 4x4
  * stride-2 padding-1 transposed conv (transposed = 1); optional ReLU.

@@ -305,6 +305,40 @@ ffv_status ffv_kernel_stats(ffv_net* net, const char* name, int64_t* launches, d
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// Multi-view cluster frame.
+extern "C" ffv_status ffv_stitch_cluster(const float* real_view, const float* const* left,
+                                         const float* const* right, int32_t n_per_side,
+                                         int32_t height, int32_t width, float* out, void* stream) {
+  using namespace ffv;
+  if (!real_view || !left || !right || !out) return fail(FFV_ERR_ARG, "null argument");
+  int g = 0;
+  for (int k : {1, 2, 4, 8})
+    if (k * k == n_per_side) g = k;
+  if (g == 0) return fail(FFV_ERR_ARG, "n_per_side must be 1, 4, 16 or 64");
+  if (height <= 0 || width <= 0 || height % g != 0 || width % g != 0)
+    return fail(FFV_ERR_ARG, "height and width must be positive multiples of sqrt(n_per_side)");
+  if (3L * height * width > (1L << 31)) return fail(FFV_ERR_ARG, "image too large");
+  StitchArgs a{};
+  a.hr = real_view;
+  a.n = n_per_side;
+  a.g = g;
+  a.H = height;
+  a.W = width;
+  a.out = out;
+  for (int i = 0; i < n_per_side; ++i) {
+    if (!left[i] || !right[i]) return fail(FFV_ERR_ARG, "null view pointer");
+    a.views[i] = left[i];
+    a.views[n_per_side + i] = right[i];
+    if (g == 4 && ((reinterpret_cast<uintptr_t>(left[i]) | reinterpret_cast<uintptr_t>(right[i])) & 15))
+      return fail(FFV_ERR_ARG, "views must be 16-byte aligned");
+  }
+  const hipError_t err = launch_stitch(a, (hipStream_t)stream);
+  if (err != hipSuccess) return fail(FFV_ERR_DEVICE, hipGetErrorString(err));
+  g_last_error.clear();
+  return FFV_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Operator-level entry point (kernel unit tests).
 extern "C" ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, int32_t cin,
                                   int32_t h, int32_t w, const float* weight, const float* bias,

@@ -112,6 +112,16 @@ hipError_t launch_flow_down(const float* in, int in_ld, int n_img, int h, int w,
 hipError_t launch_ctx_warp(const ViewDesc* views, int n_views, const CamDev* cams, int level, int C,
                            const float* flow, int h, int w, void* dst, int dst_ld,
                            long dst_img_stride, DType dt, hipStream_t s);
+// Multi-view cluster frame: [left block | real view | right block], each
+// side g*g views box-downscaled by g and tiled in raster order.
+struct StitchArgs {
+  const float* hr;          // planar [3][H][W]
+  const float* views[128];  // left side 0 .. n-1, right side n .. 2n-1
+  int n, g, H, W;           // n = g*g views per side
+  float* out;               // planar [3][H][3W]
+};
+hipError_t launch_stitch(const StitchArgs& a, hipStream_t s);
+
 // Blend-only output: I2 (padded NHWC, 4 floats) cropped to planar [3][H][W]
 // at each view's out pointer.
 hipError_t launch_blend_out(const float* I2, const ViewDesc* views, int n_img, int Hp, int Wp, int H,

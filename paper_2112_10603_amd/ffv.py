@@ -28,7 +28,7 @@ EXPORTS = ["ffv_default_opts", "ffv_create_net", "ffv_destroy_net", "ffv_interpo
            "ffv_last_error", "ffv_calibrate", "ffv_register_camera", "ffv_submit", "ffv_poll", "ffv_serving_stats",
            "ffv_debug_tap", "ffv_set_debug", "ffv_set_profiling", "ffv_kernel_stats", "ffv_op_conv",
            "ffv_autotune", "ffv_save_tuning", "ffv_load_tuning", "ffv_interpolate_blend",
-           "ffv_interpolate_recursive"]
+           "ffv_interpolate_recursive", "ffv_stitch_cluster"]
 
 
 class FfvError(RuntimeError):
@@ -103,6 +103,9 @@ def lib() -> ctypes.CDLL:
     L.ffv_interpolate_blend.restype = c_int
     L.ffv_interpolate_recursive.argtypes = [c_void, ctypes.POINTER(ffv_pair), c_int, c_int, c_void]
     L.ffv_interpolate_recursive.restype = c_int
+    L.ffv_stitch_cluster.argtypes = [c_void, ctypes.POINTER(c_void), ctypes.POINTER(c_void), c_int,
+                                     c_int, c_int, c_void, c_void]
+    L.ffv_stitch_cluster.restype = c_int
     L.ffv_save_tuning.argtypes = [c_void, ctypes.c_char_p]
     L.ffv_save_tuning.restype = c_int
     L.ffv_load_tuning.argtypes = [c_void, ctypes.c_char_p, ctypes.POINTER(c_int)]
@@ -329,3 +332,25 @@ def op_conv(x: torch.Tensor, weight, bias, stride: int = 1, transposed: bool = F
                              wt.ctypes.data, bs.ctypes.data, cout, stride, 1 if transposed else 0,
                              1 if relu else 0, n_tile, tile_w, y.data_ptr(), s.cuda_stream))
     return y
+
+
+def stitch_cluster(real_view: torch.Tensor, left, right, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Cluster frame [3, H, 3W] = [left block | real view | right block] of
+    the library's stitch kernel; ``left``/``right``: lists of g*g [3, H, W]
+    float32 CUDA views."""
+    _dev_f32(real_view, "real_view")
+    left, right = list(left), list(right)
+    _, H, W = real_view.shape
+    for v in left + right:
+        _dev_f32(v, "view")
+        if v.shape != real_view.shape:
+            raise ValueError("views must match the real view's shape")
+    if out is None:
+        out = torch.empty((3, H, 3 * W), dtype=torch.float32, device=real_view.device)
+    _dev_f32(out, "out")
+    la = (ctypes.c_void_p * max(1, len(left)))(*[v.data_ptr() for v in left])
+    ra = (ctypes.c_void_p * max(1, len(right)))(*[v.data_ptr() for v in right])
+    s = torch.cuda.current_stream(real_view.device)
+    _check(lib().ffv_stitch_cluster(real_view.data_ptr(), la, ra, len(left), H, W, out.data_ptr(),
+                                    s.cuda_stream))
+    return out
