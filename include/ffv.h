@@ -132,8 +132,9 @@ ffv_status ffv_interpolate_recursive(ffv_net* net, const ffv_pair* views, int32_
 
 /*
  * Conv tile autotuning (the conv kernel is instantiated for 256-pixel M tiles
- * with 256/128/64/32-channel N tiles; the 256 pixels form a tile_w-wide 2-D
- * block). Runs the call exactly as ffv_interpolate does (same arguments, same
+ * with 256/128/64/32-channel N tiles, halo variants with 256/128/32
+ * channels and resident-weight variants with 64/32; the 256 pixels form a
+ * tile_w-wide 2-D block). Runs the call exactly as ffv_interpolate does (same arguments, same
  * result in *out*), then re-launches each convolution of that call with
  * every candidate (N tile at most twice the real channel count rounded to
  * 32; pixel-block widths 8, 16, 32, 64 within 10 % of the least padding),
@@ -148,7 +149,9 @@ ffv_status ffv_autotune(ffv_net* net, const ffv_pair* views, int32_t n_pairs, co
 
 /*
  * Tuning table as text, one line per launch shape:
- * "layer fp8 Ho Wo n_img n_tile tile_w" ('#' starts a comment line).
+ * "layer fp8 Ho Wo n_img n_tile tile_w" ('#' starts a comment line); n_tile
+ * is 256, 128, 64, 32, or h256, h128, h32 for the halo variants, or r64, r32
+ * for the resident-weight variants.
  * ffv_save_tuning writes the net's table; ffv_load_tuning merges a file's
  * entries into it (*n_loaded, nullable, = entries read) and rejects the
  * whole file on a malformed line, an unknown layer or a tile that does not
@@ -275,6 +278,9 @@ ffv_status ffv_stitch_cluster(const float* real_view, const float* const* left,
                               const float* const* right, int32_t n_per_side, int32_t height,
                               int32_t width, float* out, void* stream);
 
+/* Flag for ffv_op_conv's precision argument (see there). */
+#define FFV_OP_ACT_OUT 0x100
+
 /*
  * One convolution layer through the library's implicit-GEMM kernel (kernel
  * unit tests). 3x3 conv, padding 1, stride 1 or 2 (transposed = 0), or 4x4
@@ -285,10 +291,18 @@ ffv_status ffv_stitch_cluster(const float* real_view, const float* const* left,
  *   y:      DEVICE float32 planar [n][cout][ho][wo], ho = (h-1)/stride+1
  *           (conv) or 2h (transposed)
  * precision: FFV_FP32 or FFV_BF16 (inputs and weights rounded to bf16, fp32
- * accumulation and output). n_tile (0 = the layer's default, else 256, 128,
+ * accumulation and output), optionally or'ed with FFV_OP_ACT_OUT: the layer
+ * writes its output in the activation dtype (bf16 for FFV_BF16), as the
+ * network's layers do, and y receives those values widened to float32. n_tile (0 = the layer's default, else 256, 128,
  * 64 or 32 output channels per workgroup, or 1 = the halo-reuse kernel:
  * 32 channels of a 16x16 pixel block, for stride-1 convs whose input
- * channels are a multiple of the K step) and tile_w (0 = default, else the
+ * channels are a multiple of the K step; 2 and 3 = the 128- and 256-channel
+ * tiles reading each channel slice's input halo once, for stride-1 and
+ * transposed convs whose input channels are a multiple of the K step, with
+ * tile_w 8, 16 or 32; 4 and 5 = the persistent kernel with the layer's
+ * weights resident in LDS, 32 or 64 GEMM columns, for stride-1 and
+ * phase-merged transposed convs with few output channels; a variant that
+ * cannot run the layer gives FFV_ERR_DEVICE) and tile_w (0 = default, else the
  * width of the 256-pixel block of a workgroup, a divisor of 256) pick the
  * kernel variant, as autotuning does; every choice gives the same result.
  * Allocates temporaries; synchronises `stream`.

@@ -346,11 +346,14 @@ extern "C" ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, 
                                   int32_t n_tile, int32_t tile_w, float* y, void* stream) {
   using namespace ffv;
   if (!x || !weight || !bias || !y) return fail(FFV_ERR_ARG, "null argument");
+  const bool act_out = (precision & FFV_OP_ACT_OUT) != 0;
+  precision &= ~FFV_OP_ACT_OUT;
   if (precision != FFV_FP32 && precision != FFV_BF16) return fail(FFV_ERR_ARG, "precision");
   if (n <= 0 || cin <= 0 || h <= 0 || w <= 0 || cout <= 0) return fail(FFV_ERR_ARG, "sizes");
   if (!transposed && stride != 1 && stride != 2) return fail(FFV_ERR_ARG, "stride");
-  if (n_tile != 0 && n_tile != 1 && n_tile != 32 && n_tile != 64 && n_tile != 128 && n_tile != 256)
-    return fail(FFV_ERR_ARG, "n_tile must be 0, 1, 32, 64, 128 or 256");
+  if (n_tile != 0 && (n_tile < 1 || n_tile > 5) && n_tile != 32 && n_tile != 64 && n_tile != 128 &&
+      n_tile != 256)
+    return fail(FFV_ERR_ARG, "n_tile must be 0, 1-5, 32, 64, 128 or 256");
   if (tile_w < 0 || tile_w > 256 || (tile_w > 0 && 256 % tile_w != 0))
     return fail(FFV_ERR_ARG, "tile_w must be 0 or divide 256");
   const DType dt = precision == FFV_FP32 ? DType::F32 : DType::BF16;
@@ -379,7 +382,9 @@ extern "C" ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, 
   hipError_t err = hipMalloc(&xin, (size_t)n * h * w * L.cin_pad * e);
   if (err == hipSuccess) err = hipMalloc(&wd, packed.size());
   if (err == hipSuccess) err = hipMalloc(&bd, (size_t)cout * 4);
-  if (err == hipSuccess) err = hipMalloc(&yo, (size_t)n * ho * wo * cout * 4);
+  // output as the network's layers write it (activation dtype), or float
+  const DType out_dt = act_out ? dt : DType::F32;
+  if (err == hipSuccess) err = hipMalloc(&yo, (size_t)n * ho * wo * cout * dtype_size(out_dt));
   if (err == hipSuccess) err = hipMalloc(&zr, 256);
   if (err == hipSuccess) err = hipMemset(zr, 0, 256);
   if (err == hipSuccess) err = hipMemcpy(wd, packed.data(), packed.size(), hipMemcpyHostToDevice);
@@ -411,7 +416,7 @@ extern "C" ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, 
     a.stride = L.transposed ? 1 : stride;
     a.transposed = L.mode;
     a.relu = relu ? 1 : 0;
-    a.out_f32 = 1;
+    a.out_f32 = out_dt == DType::F32 ? 1 : 0;
     a.accumulate = 0;
     a.taps = L.mode == 1 ? 4 : 9;
     a.zero = zr;
@@ -425,10 +430,16 @@ extern "C" ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, 
       tile = ConvTile::H32;
       a.tile_w = 16;
     }
+    if (n_tile == 2) tile = ConvTile::H128;
+    if (n_tile == 3) tile = ConvTile::H256;
+    if (n_tile == 4 || n_tile == 5) {
+      tile = n_tile == 4 ? ConvTile::R32 : ConvTile::R64;
+      a.tile_w = 16;
+    }
     err = launch_conv(dt, tile, a, s);
   }
   for (int i = 0; err == hipSuccess && i < n; ++i)
-    err = launch_extract((const float*)yo + (size_t)i * ho * wo * cout, DType::F32, cout, cout,
+    err = launch_extract((const char*)yo + (size_t)i * ho * wo * cout * dtype_size(out_dt), out_dt, cout, cout,
                          (long)ho * wo, y + (size_t)i * cout * ho * wo, s);
   if (err == hipSuccess) err = hipStreamSynchronize(s);
   cleanup();

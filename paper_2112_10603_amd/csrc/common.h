@@ -62,12 +62,31 @@ struct ConvArgs {
   const void* zero;     // >= 16 bytes of zeros (read for taps outside the image)
 };
 
-// N-tile widths the conv kernel is instantiated for (the M tile is 256), and
+// N-tile widths the conv kernel is instantiated for (the M tile is 256);
 // H32: the halo-reuse kernel (16x16 output pixels x 32 channels, stride-1
-// 3x3 neighbourhoods only; the M-tile width must be 16).
-enum class ConvTile : int { N256 = 0, N128 = 1, N64 = 2, N32 = 3, H32 = 4 };
+// 3x3 neighbourhoods only; the M-tile width must be 16); H256, H128: the
+// conv kernel's halo variant with 256/128-channel N tiles (stride-1 3x3
+// neighbourhoods and per-phase transposed convs; M-tile width 8, 16 or 32);
+// R32, R64: the persistent halo kernel with the layer's weights resident in
+// LDS (stride-1 3x3 neighbourhoods with at most 32/64 GEMM columns and small
+// weights; M-tile width 16).
+enum class ConvTile : int { N256 = 0, N128 = 1, N64 = 2, N32 = 3, H32 = 4, H256 = 5, H128 = 6, R32 = 7, R64 = 8 };
+// N tile (output channels per workgroup) of a tile kind.
+inline int conv_tile_bn(ConvTile t) {
+  switch (t) {
+    case ConvTile::N256: case ConvTile::H256: return 256;
+    case ConvTile::N128: case ConvTile::H128: return 128;
+    case ConvTile::N64: case ConvTile::R64: return 64;
+    default: return 32;
+  }
+}
 // Whether the halo-reuse kernel can run a launch (tile_w is not checked).
 bool conv_halo_ok(DType dt, const ConvArgs& a);
+// Whether the H256/H128 halo variant can run a launch (tile_w checked).
+bool conv_halo_tile_ok(DType dt, const ConvArgs& a);
+// Whether the resident-weight kernel with a bn-channel N tile (32 or 64) can
+// run a launch (tile_w is not checked: the kernel's block is 16 x 16).
+bool conv_resident_ok(DType dt, const ConvArgs& a, int bn);
 
 hipError_t launch_conv(DType dt, ConvTile tile, const ConvArgs& a, hipStream_t s);
 // Width of the 2-D pixel block of a 256-pixel M tile for a Ho x Wo grid:

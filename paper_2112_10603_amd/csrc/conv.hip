@@ -4,6 +4,7 @@
 // packing's K order depends on.
 #include "conv_halo.h"
 #include "conv_kernel.h"
+#include "conv_resident.h"
 
 namespace ffv {
 
@@ -23,6 +24,14 @@ hipError_t launch_t(ConvTile tile, const ConvArgs& a, hipStream_t s) {
       return launch_variant<T, 256, 32, 8, 1, 128, 2, 1>(a, s);
     case ConvTile::H32:
       return launch_halo<T>(a, s);
+    case ConvTile::H256:
+      return launch_variant<T, 256, 256, 4, 2, 128, 2, 1, true>(a, s);
+    case ConvTile::H128:
+      return launch_variant<T, 256, 128, 4, 2, 128, 2, 1, true>(a, s);
+    case ConvTile::R32:
+      return launch_resident<T, 32>(a, s);
+    case ConvTile::R64:
+      return launch_resident<T, 64>(a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -30,6 +39,14 @@ hipError_t launch_t(ConvTile tile, const ConvArgs& a, hipStream_t s) {
 }  // namespace
 
 int conv_k_step(DType dt) { return dt == DType::F32 ? 32 : (dt == DType::BF16 ? 64 : 128); }
+
+bool conv_halo_tile_ok(DType dt, const ConvArgs& a) { return convk::halo_tile_ok(a, conv_k_step(dt)); }
+
+bool conv_resident_ok(DType dt, const ConvArgs& a, int bn) {
+  ConvArgs b = a;
+  b.tile_w = convk::Resident::TW;
+  return convk::resident_ok(b, bn, (int)dtype_size(dt));
+}
 
 bool conv_halo_ok(DType dt, const ConvArgs& a) {
   ConvArgs b = a;

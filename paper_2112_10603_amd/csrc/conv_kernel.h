@@ -31,6 +31,15 @@
 // output channels in bf16/fp8 feed the weights as the MFMA's A operand, so
 // a lane ends with consecutive output channels of one pixel; their
 // epilogue stages the output tile through LDS and writes 16-byte chunks.
+//
+// HALO variant (3x3 stride-1 convs, per-phase and phase-merged transposed
+// convs, whose channels are a multiple of the K step): the M tile's input
+// halo ((TH + 2) x (TW + 2) pixels of one channel slice) is loaded into LDS
+// once per slice, and every tap of the slice reads its shifted window of
+// it, so the A bytes per slice drop from taps x BM rows to the halo's rows.
+// The next slice's halo is loaded in pieces, one share per tap step of the
+// current slice, into the second halo buffer; the weight tiles keep the
+// two-stage ring of the generic kernel.
 #pragma once
 
 #include "common.h"
@@ -151,9 +160,15 @@ struct Conv {
   __device__ static inline int logical_chunk(int row, int phys) { return phys ^ key(row); }
 };
 
-template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES, int SWZ, bool SW>
+// Halo rows of an LDS buffer of the HALO variant: the largest
+// (256/TW + 2) x (TW + 2) over the tile widths it accepts (8, 16, 32).
+constexpr int kHaloRows = 340;
+__host__ __device__ constexpr bool halo_width_ok(int tw) { return tw == 8 || tw == 16 || tw == 32; }
+
+template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES, int SWZ, bool SW, bool HALO>
 __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   using C = Conv<T, BM, BN, WM, WN, KB, STAGES, SWZ>;
+  static_assert(!HALO || (BM == 256 && STAGES == 2), "halo tiles: 256 pixels, two stages");
   constexpr int NT = C::NT, CH = C::CH, BK = C::BK, VEC = C::VEC;
   // SW: the MFMAs take the weights as A (each lane then holds consecutive
   // channels of one pixel) and the output tile is staged through LDS for
@@ -164,12 +179,14 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   constexpr int A_IT = C::A_IT, B_IT = C::B_IT;
   constexpr int A_VECS = C::A_VECS, B_VECS = C::B_VECS;
 
-  // the A/B rings, reused by the staged epilogue (BM x BN 2-byte values)
-  constexpr int RING_VECS = STAGES * (BM + BN) * CH;
+  // the A/B rings, reused by the staged epilogue (BM x BN 2-byte values);
+  // an A buffer holds BM rows, or a slice's halo in the HALO variant
+  constexpr int AROWS = HALO ? kHaloRows : BM;
+  constexpr int RING_VECS = STAGES * (AROWS + BN) * CH;
   constexpr int SMEM_VECS = (SW && BM * BN * 2 / 16 > RING_VECS) ? BM * BN * 2 / 16 : RING_VECS;
   __shared__ __attribute__((aligned(16))) uint4 smem[SMEM_VECS];
-  uint4 (*As)[BM * CH] = reinterpret_cast<uint4 (*)[BM * CH]>(smem);
-  uint4 (*Bs)[BN * CH] = reinterpret_cast<uint4 (*)[BN * CH]>(smem + STAGES * BM * CH);
+  uint4 (*As)[AROWS * CH] = reinterpret_cast<uint4 (*)[AROWS * CH]>(smem);
+  uint4 (*Bs)[BN * CH] = reinterpret_cast<uint4 (*)[BN * CH]>(smem + STAGES * AROWS * CH);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -218,7 +235,7 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   int a_pix[A_IT], a_tap[A_IT], a_c[A_IT];
   uint32_t a_mask[A_IT];
 #pragma unroll
-  for (int i = 0; i < A_IT; ++i) {
+  for (int i = 0; i < (HALO ? 0 : A_IT); ++i) {
     const int v = tid + i * NT;
     const int row = v / CH;
     const int oy = ty0 + row / TW, ox = tx0 + row % TW;
@@ -237,6 +254,30 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
     a_tap[i] = kk / a.cin_pad;
     a_c[i] = kk - a_tap[i] * a.cin_pad;
   }
+  // HALO: load i of a slice fills halo slot tid + i*NT = (halo row, physical
+  // chunk); h_off is its input offset in the image (-1: outside the image
+  // or past the halo); hb[i] the halo row of fragment i's pixel at tap
+  // offset (0, 0).
+  constexpr int HA_IT = HALO ? (kHaloRows * CH + NT - 1) / NT : 1;
+  const int hwid = a.tile_w + 2;
+  const int h_vecs = (BM / a.tile_w + 2) * hwid * CH;
+  int h_off[HA_IT];
+  int hb[FM];
+  if constexpr (HALO) {
+#pragma unroll
+    for (int i = 0; i < HA_IT; ++i) {
+      const int v = tid + i * NT;
+      const int hrow = v / CH;
+      const int iy = ty0 - 1 + hrow / hwid, ix = tx0 - 1 + hrow % hwid;
+      const bool ok = v < h_vecs && iy >= 0 && iy < a.Hi && ix >= 0 && ix < a.Wi;
+      h_off[i] = ok ? (iy * a.Wi + ix) * a.in_ld + C::logical_chunk(hrow, chunk) * VEC : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+      const int p = wm * TM + i * 32 + (lane & 31);
+      hb[i] = (p / TW + 1) * hwid + p % TW + 1;
+    }
+  }
   const T* b_ptr[B_IT];
 #pragma unroll
   for (int i = 0; i < B_IT; ++i) {
@@ -252,6 +293,26 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
 
   // Issue the loads of K step kc into ring buffer buf. Steps are issued in
   // increasing order, one at a time (the tap-major counters advance here).
+  const T* in_img = in + (long)img_t * a.in_img_stride;
+  // HALO: the weight tile of step kc, and the halo loads of slice `slice`
+  // whose index is congruent to `part` modulo the tap count (part < 0: all)
+  auto issue_b = [&](int kc, int buf) {
+#pragma unroll
+    for (int i = 0; i < B_IT; ++i) {
+      const T* src = b_ptr[i] + (long)kc * BK;
+      if (B_VECS % NT == 0 || tid + i * NT < B_VECS) load_to_lds(src, &Bs[buf][i * NT + wave * 64]);
+    }
+  };
+  auto issue_halo = [&](int slice, int buf, int part) {
+#pragma unroll
+    for (int i = 0; i < HA_IT; ++i) {
+      if (part >= 0 && i % a.taps != part) continue;
+      if (i * NT >= h_vecs) continue;
+      const T* src = h_off[i] >= 0 ? in_img + (h_off[i] + slice * BK) : zero;
+      if (tid + i * NT < h_vecs) load_to_lds(src, &As[buf][i * NT + wave * 64]);
+    }
+  };
+
   auto issue = [&](int kc, int buf) {
     if (tap_uniform) {
       // channel-slice major: all taps of a BK-channel slice back to back, so
@@ -300,7 +361,10 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
 
-  auto compute = [&](int buf) {
+  // A fragment row of fragment i: the tile row, or (HALO) the halo row of
+  // the pixel shifted by this step's tap offset hoff
+  auto arow = [&](int i, int hoff) { return HALO ? hb[i] + hoff : wm * TM + i * 32 + lrow; };
+  auto compute = [&](int buf, int abuf, int hoff) {
     if constexpr (sizeof(T) == 1) {
       // fp8: a lane half's CH/2 chunks feed CH/4 MFMAs of two chunks each
 #pragma unroll
@@ -309,8 +373,8 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
         uint4 fa[FM][2], fb[FN][2];
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
-          fa[i][0] = As[buf][C::swz(wm * TM + i * 32 + lrow, ch)];
-          fa[i][1] = As[buf][C::swz(wm * TM + i * 32 + lrow, ch + 1)];
+          fa[i][0] = As[abuf][C::swz(arow(i, hoff), ch)];
+          fa[i][1] = As[abuf][C::swz(arow(i, hoff), ch + 1)];
         }
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
@@ -333,7 +397,7 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
         const int ch = lhalf * (CH / 2) + s;
         uint4 fa[FM], fb[FN];
 #pragma unroll
-        for (int i = 0; i < FM; ++i) fa[i] = As[buf][C::swz(wm * TM + i * 32 + lrow, ch)];
+        for (int i = 0; i < FM; ++i) fa[i] = As[abuf][C::swz(arow(i, hoff), ch)];
 #pragma unroll
         for (int j = 0; j < FN; ++j) fb[j] = Bs[buf][C::swz(wn * TN + j * 32 + lrow, ch)];
 #pragma unroll
@@ -354,18 +418,34 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   // compiler's view, so the waits for them are explicit: before the barrier
   // of step k, at most the loads of the younger steps may be outstanding
   // (vmcnt drains in issue order).
-  constexpr int LPS = A_IT + B_IT;  // loads per step per thread
-#pragma unroll
-  for (int st = 0; st < STAGES - 1; ++st)
-    if (st < nk) issue(st, st);
-  for (int kc = 0; kc < nk; ++kc) {
-    if (kc + STAGES - 2 < nk)
-      wait_vm<(STAGES - 2) * LPS>();
-    else
+  if constexpr (HALO) {
+    // two weight stages and two halo buffers; every load of step kc is
+    // waited for (vmcnt 0) before the barrier of step kc + 1
+    const int n_slices = a.cin_pad / BK;
+    issue_b(0, 0);
+    if (n_slices > 0) issue_halo(0, 0, -1);
+    for (int kc = 0; kc < nk; ++kc) {
       wait_vm<0>();
-    __syncthreads();
-    if (kc + STAGES - 1 < nk) issue(kc + STAGES - 1, (kc + STAGES - 1) % STAGES);
-    compute(kc % STAGES);
+      __syncthreads();
+      const int slice = kc / a.taps, tap = kc - slice * a.taps;
+      if (kc + 1 < nk) issue_b(kc + 1, (kc + 1) & 1);
+      if (slice + 1 < n_slices) issue_halo(slice + 1, (slice + 1) & 1, tap);
+      compute(kc & 1, slice & 1, tap_dy(tap) * hwid + tap_dx(tap));
+    }
+  } else {
+    constexpr int LPS = A_IT + B_IT;  // loads per step per thread
+#pragma unroll
+    for (int st = 0; st < STAGES - 1; ++st)
+      if (st < nk) issue(st, st);
+    for (int kc = 0; kc < nk; ++kc) {
+      if (kc + STAGES - 2 < nk)
+        wait_vm<(STAGES - 2) * LPS>();
+      else
+        wait_vm<0>();
+      __syncthreads();
+      if (kc + STAGES - 1 < nk) issue(kc + STAGES - 1, (kc + STAGES - 1) % STAGES);
+      compute(kc % STAGES, kc % STAGES, 0);
+    }
   }
 
   if constexpr (!SW) {
@@ -505,9 +585,21 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   }
 }
 
-template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES, int SWZ = 0>
+// Whether the HALO variant covers a launch: a stride-1 3x3 neighbourhood
+// (plain, per-phase transposed with 4 taps, or phase-merged), channel
+// slices that are whole K steps in slice-major K order, and a tile width
+// whose halo fits the buffer.
+inline bool halo_tile_ok(const ConvArgs& a, int bk) {
+  const bool nb = (a.transposed == 0 && a.stride == 1 && a.taps == 9) ||
+                  (a.transposed == 1 && a.taps == 4) || (a.transposed == 2 && a.taps == 9);
+  return nb && a.cin_pad % bk == 0 && a.K_pad == a.taps * a.cin_pad && a.Hi == a.Ho && a.Wi == a.Wo &&
+         halo_width_ok(a.tile_w);
+}
+
+template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES, int SWZ = 0, bool HALO = false>
 hipError_t launch_variant(const ConvArgs& a, hipStream_t s) {
   using C = Conv<T, BM, BN, WM, WN, KB, STAGES, SWZ>;
+  if (HALO && !halo_tile_ok(a, C::BK)) return hipErrorInvalidValue;
   const int phases = a.transposed == 1 ? 4 : 1;
   const int n_tiles = (a.n_rows + BN - 1) / BN;
   // every B row a tile reads (n_tiles * BN of them) must exist in the packed weights
@@ -526,12 +618,13 @@ hipError_t launch_variant(const ConvArgs& a, hipStream_t s) {
                       a.cout % run == 0 && a.out_ld % run == 0;
   if constexpr (sizeof(T) != 4 && BN >= 128) {
     if (staged) {
-      hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES, SWZ, true>), grid, dim3(C::NT), 0, s,
-                         a);
+      hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES, SWZ, true, HALO>), grid, dim3(C::NT), 0,
+                         s, a);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES, SWZ, false>), grid, dim3(C::NT), 0, s, a);
+  hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES, SWZ, false, HALO>), grid, dim3(C::NT), 0, s,
+                     a);
   return hipGetLastError();
 }
 

@@ -1,0 +1,382 @@
+// Persistent halo-reuse convolution with the weights resident in LDS, for
+// layers with few output channels over a stride-1 3x3 neighbourhood whose
+// whole weight matrix fits next to two input halos (supplementary layer
+// table: the flow/mask heads of the VIBlocks, phase-merged 4x4 transposed
+// convs, and the stride-1 3x3 convs of the narrow U-Net levels).
+//
+// These layers have one or two channel slices per output block, so a
+// kernel that loads each block's input and weights and then computes has
+// nothing to hide the load latency behind: one slice's MFMAs are a few
+// hundred cycles, one load round trip from HBM several thousand. Here a
+// workgroup stays resident on its compute unit, loads the weights once, and
+// walks a range of 16x16 output blocks with one pipeline of channel-slice
+// steps that runs across block boundaries: while it computes the last slice
+// of a block, the first slice's halo of its next block is already loading,
+// and the block's epilogue (registers straight to global memory) overlaps
+// that load as well. Every tap reads its shifted window of the halo from
+// LDS (as in the non-resident halo kernel), and its weights from the
+// resident copy.
+#pragma once
+
+#include "conv_halo.h"
+
+namespace ffv {
+namespace convk {
+
+struct Resident {
+  static constexpr int NT = 512;                     // 8 waves
+  static constexpr int TW = 16, TH = 16;             // output block
+  static constexpr int HW = TW + 2;                  // halo row width
+  static constexpr int NH = HW * (TH + 2);           // halo pixels
+  static constexpr int KB = 128;                     // bytes of a pixel's channel slice
+  static constexpr int CH = KB / 16;
+  static constexpr int A_VECS = NH * CH;
+  static constexpr int A_IT = (A_VECS + NT - 1) / NT;
+  // resident weights: BN rows of K_pad values, 16-byte chunks, row pitch
+  // one chunk longer than the row (odd pitch: the 32 rows a fragment read
+  // touches fall in distinct bank groups, 16 at a time)
+  static constexpr int W_VECS = 4800;
+};
+
+// Whether the resident kernel with an N tile of bn channels covers a launch
+// (the weights of every output channel must fit the resident buffer).
+inline bool resident_ok(const ConvArgs& a, int bn, int elem_bytes) {
+  const int bk = Resident::KB / elem_bytes;
+  const bool s1 = (a.transposed == 0 && a.stride == 1) || a.transposed == 2;
+  const long row_bytes = (long)a.K_pad * elem_bytes;
+  if (!s1 || a.taps != 9 || a.cin_pad % bk != 0 || a.K_pad != 9 * a.cin_pad || row_bytes % 16 != 0)
+    return false;
+  const long rc = row_bytes / 16;
+  return a.Hi == a.Ho && a.Wi == a.Wo && a.n_rows <= bn && bn <= a.cout_pad &&
+         bn * (rc + 1) <= Resident::W_VECS && a.tile_w == Resident::TW;
+}
+
+// Two waves per SIMD is all the LDS footprint allows; saying so lets the
+// compiler keep a second tap's fragments in registers. SW: the weights are
+// the MFMA's A operand, so a lane ends with runs of 4 consecutive output
+// channels of one pixel, and the epilogue stages each wave's 32 x BN output
+// tile through LDS for 16-byte stores (bf16/fp8 outputs in 16-byte channel
+// runs); otherwise lanes store single values from registers.
+template <typename T, int BN, bool SW>
+__global__ __launch_bounds__(Resident::NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void conv_resident(ConvArgs a, int n_tiles) {
+  using R = Resident;
+  constexpr int NT = R::NT, CH = R::CH, TW = R::TW, TH = R::TH, HW = R::HW;
+  constexpr int A_IT = R::A_IT, A_VECS = R::A_VECS, FN = BN / 32;
+  constexpr int BK = R::KB / (int)sizeof(T), VEC = 16 / (int)sizeof(T);
+
+  __shared__ __attribute__((aligned(16))) uint4 Wl[R::W_VECS];
+  __shared__ __attribute__((aligned(16))) uint4 Ah[2][A_VECS];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lrow = lane & 31, lhalf = lane >> 5;
+  const int merged = a.transposed == 2;
+  const int rc = a.K_pad * (int)sizeof(T) / 16, rcp = rc + 1;
+  const int n_slices = a.cin_pad / BK;
+
+  // This workgroup's blocks: each XCD (workgroups round-robin over 8) owns a
+  // contiguous range of blocks, so neighbouring blocks' shared halo rows
+  // meet in its L2; its workgroups take the range's blocks in turn.
+  const int G = gridDim.x, b = blockIdx.x;
+  int t_first = b, t_step = G, t_end = n_tiles;
+  if (G % 8 == 0) {
+    const int x = b & 7, q = n_tiles >> 3, r = n_tiles & 7;
+    const int base = x * q + min(x, r);
+    t_first = base + (b >> 3);
+    t_step = G >> 3;
+    t_end = base + q + (x < r ? 1 : 0);
+  }
+  const int tiles_x = (a.Wo + TW - 1) / TW, tiles_y = (a.Ho + TH - 1) / TH;
+  const int per_img = tiles_x * tiles_y;
+
+  const T* in = reinterpret_cast<const T*>(a.in);
+  const T* wgt = reinterpret_cast<const T*>(a.wgt);
+  const T* zero = reinterpret_cast<const T*>(a.zero);
+
+  // resident weights: slot v = (row v / rcp, chunk v % rcp); the pitch's
+  // last chunk is never written or read
+  for (int v0 = 0; v0 < BN * rcp; v0 += NT) {
+    const int v = v0 + tid;
+    const int row = v / rcp, c = v - row * rcp;
+    if (v < BN * rcp && c < rc) load_to_lds(wgt + (long)row * a.K_pad + c * VEC, &Wl[v0 + wave * 64]);
+  }
+
+  // halo slot tid + i*NT = (halo row, physical chunk tid % CH): its place in
+  // the 18x18 halo and the channel offset of the chunk stored there
+  const int chunk = tid % CH;
+  int h_y[A_IT], h_x[A_IT], h_c[A_IT];
+#pragma unroll
+  for (int i = 0; i < A_IT; ++i) {
+    const int hrow = (tid + i * NT) / CH;
+    h_y[i] = hrow / HW;
+    h_x[i] = hrow % HW;
+    h_c[i] = (chunk ^ Halo::key(hrow)) * VEC;
+  }
+  auto issue_halo = [&](int t, int s, int buf) {
+    const int img = t / per_img, rem = t - img * per_img;
+    const int ty0 = (rem / tiles_x) * TH, tx0 = (rem % tiles_x) * TW;
+    const T* src0 = in + (long)img * a.in_img_stride + s * BK;
+#pragma unroll
+    for (int i = 0; i < A_IT; ++i) {
+      const int iy = ty0 - 1 + h_y[i], ix = tx0 - 1 + h_x[i];
+      const bool ok = tid + i * NT < A_VECS && iy >= 0 && iy < a.Hi && ix >= 0 && ix < a.Wi;
+      const T* src = ok ? src0 + ((iy * a.Wi + ix) * a.in_ld + h_c[i]) : zero;
+      if (A_VECS % NT == 0 || tid + i * NT < A_VECS) load_to_lds(src, &Ah[buf][i * NT + wave * 64]);
+    }
+  };
+
+  // this lane's output pixel (A fragment row) in the block
+  const int prow = wave * 32 + lrow;
+  const int py = prow / TW, pxx = prow % TW;
+  f32x16 acc[FN];
+#pragma unroll
+  for (int f = 0; f < FN; ++f)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[f][e] = 0.f;
+
+  // A tap's fragments (this lane half's CH/2 chunks of the pixel, and of
+  // each weight row) are read into one register set while the MFMAs of the
+  // previous tap consume the other, so LDS latency is not paid per MFMA.
+  constexpr int QN = CH / 2;
+  auto load_tap = [&](int buf, int s, int tap, uint4 (&fa)[QN], uint4 (&fb)[FN][QN]) {
+    const int hidx = (py + tap / 3) * HW + pxx + tap % 3;  // (y + dy + 1, x + dx + 1)
+    const int kc = (s * 9 + tap) * CH + lhalf * QN;        // (slice, tap) chunk in a weight row
+#pragma unroll
+    for (int q = 0; q < QN; ++q) fa[q] = Ah[buf][Halo::swz(hidx, lhalf * QN + q)];
+#pragma unroll
+    for (int f = 0; f < FN; ++f)
+#pragma unroll
+      for (int q = 0; q < QN; ++q) fb[f][q] = Wl[(f * 32 + lrow) * rcp + kc + q];
+  };
+  auto mma_tap = [&](const uint4 (&fa)[QN], const uint4 (&fb)[FN][QN]) {
+    if constexpr (sizeof(T) == 1) {
+#pragma unroll
+      for (int q = 0; q < QN; q += 2)
+#pragma unroll
+        for (int f = 0; f < FN; ++f) {
+          if constexpr (SW)
+            mfma_f8(acc[f], fb[f][q], fb[f][q + 1], fa[q], fa[q + 1]);
+          else
+            mfma_f8(acc[f], fa[q], fa[q + 1], fb[f][q], fb[f][q + 1]);
+        }
+    } else {
+#pragma unroll
+      for (int q = 0; q < QN; ++q)
+#pragma unroll
+        for (int f = 0; f < FN; ++f) {
+          if constexpr (SW)
+            mfma_chunk<T>(acc[f], fb[f][q], fa[q]);
+          else
+            mfma_chunk<T>(acc[f], fa[q], fb[f][q]);
+        }
+    }
+  };
+  auto compute = [&](int buf, int s) {
+    uint4 fa[2][QN], fb[2][FN][QN];
+    load_tap(buf, s, 0, fa[0], fb[0]);
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      if (tap + 1 < 9) load_tap(buf, s, tap + 1, fa[(tap + 1) & 1], fb[(tap + 1) & 1]);
+      // keep the next tap's reads ahead of this tap's MFMAs (the scheduler
+      // would otherwise sink each read to its MFMA)
+      __builtin_amdgcn_sched_barrier(0);
+      mma_tap(fa[tap & 1], fb[tap & 1]);
+    }
+  };
+
+  // Epilogue of block t, whose last slice was computed from halo buffer buf.
+  const int cout_m = merged ? a.cout : 1;
+  auto epilogue_staged = [&](int t, int buf) {
+    // lane l holds, for fragment f, pixel wave*32 + l%32 and GEMM columns
+    // f*32 + 8g + 4*(l/32) + q (g, q = 0..3). Bias, scale and ReLU in
+    // registers; the wave's 32 x BN tile goes to its own part of the halo
+    // buffer every wave has now finished with (rows of BN values, 16-byte
+    // chunks XOR-swizzled by row), and is read back as 16-byte chunks.
+    const int img = t / per_img, rem = t - img * per_img;
+    const int ty0 = (rem / tiles_x) * TH, tx0 = (rem % tiles_x) * TW;
+    const int E = a.out_scale ? 1 : 2;  // output element bytes (fp8 or bf16)
+    const int pitch = BN * E, cpr = pitch / 16;
+    char* region = reinterpret_cast<char*>(&Ah[buf][0]) + wave * 32 * pitch;
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f < FN; ++f) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int n = f * 32 + 8 * g + 4 * lhalf;  // first of 4 GEMM columns (one output phase)
+        const bool nok = n < a.n_rows;
+        const int o = nok ? (merged ? n % cout_m : n) : 0;
+        const float4 b4 = *reinterpret_cast<const float4*>(a.bias + o);
+        const float4 s4 = a.w_scale ? *reinterpret_cast<const float4*>(a.w_scale + o) : make_float4(1.f, 1.f, 1.f, 1.f);
+        const float bq[4] = {b4.x, b4.y, b4.z, b4.w}, sq[4] = {s4.x, s4.y, s4.z, s4.w};
+        float os[4] = {1.f, 1.f, 1.f, 1.f};
+        if (E == 1) {
+          const float4 o4 = *reinterpret_cast<const float4*>(a.out_scale + o);
+          os[0] = o4.x;
+          os[1] = o4.y;
+          os[2] = o4.z;
+          os[3] = o4.w;
+        }
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float x = acc[f][4 * g + q] * sq[q] + bq[q];
+          if (a.relu) x = fmaxf(x, 0.f);
+          if (a.amax && nok) atomicMax(reinterpret_cast<unsigned*>(a.amax) + o + q, __float_as_uint(fabsf(x)));
+          v[q] = x;
+        }
+        const int byte = n * E;
+        char* dst = region + lrow * pitch + (((byte >> 4) ^ (lrow & (cpr - 1))) << 4) + (byte & 15);
+        if (E == 2) {
+          uint2 w;
+          w.x = (uint32_t)__builtin_bit_cast(uint16_t, (bf16)v[0]) |
+                ((uint32_t)__builtin_bit_cast(uint16_t, (bf16)v[1]) << 16);
+          w.y = (uint32_t)__builtin_bit_cast(uint16_t, (bf16)v[2]) |
+                ((uint32_t)__builtin_bit_cast(uint16_t, (bf16)v[3]) << 16);
+          *reinterpret_cast<uint2*>(dst) = w;
+        } else {
+          uint32_t w = 0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) w |= (uint32_t)to_f8(v[q] * os[q]) << (8 * q);
+          *reinterpret_cast<uint32_t*>(dst) = w;
+        }
+      }
+    }
+    // the wave reads back only its own region: its LDS operations complete
+    // in order, so waiting for them is enough
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_wave_barrier();
+    const int run = 16 / E;
+    for (int q = lane; q < 32 * cpr; q += 64) {
+      const int p = q / cpr, ch = q - p * cpr;
+      const int row = wave * 32 + p;
+      int oy = ty0 + row / TW, ox = tx0 + row % TW;
+      const int n = ch * run;
+      if (oy >= a.Ho || ox >= a.Wo || n >= a.n_rows) continue;
+      long off;
+      if (!merged) {
+        off = ((long)oy * a.Wout + ox) * a.out_ld + n;
+      } else {
+        const int ph = n / cout_m, o = n - ph * cout_m;
+        off = ((long)(2 * oy + (ph >> 1)) * a.Wout + 2 * ox + (ph & 1)) * a.out_ld + o;
+      }
+      const uint4 w = *reinterpret_cast<const uint4*>(region + p * pitch + ((ch ^ (p & (cpr - 1))) << 4));
+      *reinterpret_cast<uint4*>(reinterpret_cast<char*>(a.out) + ((long)img * a.out_img_stride + off) * E) = w;
+    }
+#pragma unroll
+    for (int f = 0; f < FN; ++f)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[f][e] = 0.f;
+  };
+  // (pixels as A): lane l holds channel f*32 + l%32 of 16 pixels per
+  // fragment; registers straight to global memory.
+  auto epilogue = [&](int t) {
+    const int img = t / per_img, rem = t - img * per_img;
+    const int ty0 = (rem / tiles_x) * TH, tx0 = (rem % tiles_x) * TW;
+#pragma unroll
+    for (int f = 0; f < FN; ++f) {
+      const int n = f * 32 + lrow;
+      long col = 0;
+      int o = 0;
+      bool n_ok;
+      if (!merged) {
+        n_ok = n < a.cout;
+        o = n;
+        col = n;
+      } else {
+        n_ok = n < 4 * cout_m;
+        const int ph = n_ok ? n / cout_m : 0;
+        o = n - ph * cout_m;
+        col = ((long)(ph >> 1) * a.Wout + (ph & 1)) * a.out_ld + o;
+      }
+      if (!n_ok) continue;
+      const float bn = a.bias[o];
+      const float ws = a.w_scale ? a.w_scale[o] : 1.f;
+      float amax = 0.f;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int row = wave * 32 + (e >> 2) * 8 + lhalf * 4 + (e & 3);
+        int oy = ty0 + row / TW, ox = tx0 + row % TW;
+        if (oy >= a.Ho || ox >= a.Wo) continue;
+        if (merged) {  // the GEMM grid point's phase-(0, 0) output
+          oy *= 2;
+          ox *= 2;
+        }
+        float v = acc[f][e] * ws + bn;
+        if (a.relu) v = fmaxf(v, 0.f);
+        amax = fmaxf(amax, fabsf(v));
+        store_out<T>(a, (long)img * a.out_img_stride + ((long)oy * a.Wout + ox) * a.out_ld + col, o, v);
+      }
+      if (a.amax) atomicMax(reinterpret_cast<unsigned*>(a.amax) + o, __float_as_uint(amax));
+    }
+#pragma unroll
+    for (int f = 0; f < FN; ++f)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[f][e] = 0.f;
+  };
+
+  // one pipeline of (block, slice) steps; step j computes from halo buffer
+  // j & 1 while the next step's halo loads into the other one. The first
+  // wait also covers the resident weights.
+  if (t_first < t_end && n_slices > 0) issue_halo(t_first, 0, 0);
+  int j = 0;
+  for (int t = t_first; t < t_end; t += t_step) {
+    for (int s = 0; s < n_slices; ++s, ++j) {
+      wait_vm<0>();
+      __syncthreads();
+      if (s + 1 < n_slices)
+        issue_halo(t, s + 1, (j + 1) & 1);
+      else if (t + t_step < t_end)
+        issue_halo(t + t_step, 0, (j + 1) & 1);
+      compute(j & 1, s);
+    }
+    if constexpr (SW)
+      epilogue_staged(t, (j - 1) & 1);
+    else
+      epilogue(t);
+  }
+  wait_vm<0>();  // nothing outstanding when the workgroup ends
+}
+
+// Compute units of the current device (the persistent grid's size).
+inline int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      cus = n;
+    else
+      cus = 8;
+  }
+  return cus;
+}
+
+template <typename T, int BN>
+hipError_t launch_resident(const ConvArgs& a, hipStream_t s) {
+  constexpr int VEC = 16 / (int)sizeof(T);
+  if (!resident_ok(a, BN, (int)sizeof(T)) || a.n_rows <= 0 || a.in_ld % VEC != 0 || a.in_ld < a.cin_pad)
+    return hipErrorInvalidValue;
+  if ((long)a.Hi * a.Wi * a.in_ld >= (1L << 31)) return hipErrorInvalidValue;
+  const long tiles = (long)a.n_img * ((a.Ho + Resident::TH - 1) / Resident::TH) *
+                     ((a.Wo + Resident::TW - 1) / Resident::TW);
+  if (tiles > 0x7fffffffL) return hipErrorInvalidValue;
+  const int cus = device_cus();
+  const long per_xcd = cus >= 8 ? cus / 8 * 8 : cus;  // one workgroup per compute unit
+  const int grid = (int)(tiles < per_xcd ? tiles : per_xcd);
+  // the staged epilogue needs bf16/fp8 outputs in 16-byte channel runs
+  const int run = a.out_scale ? 16 : 8;
+  const bool staged = sizeof(T) != 4 && !a.out_f32 && a.cout % run == 0 && a.out_ld % run == 0;
+  if constexpr (sizeof(T) != 4) {
+    if (staged) {
+      hipLaunchKernelGGL((conv_resident<T, BN, true>), dim3(grid), dim3(Resident::NT), 0, s, a, (int)tiles);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((conv_resident<T, BN, false>), dim3(grid), dim3(Resident::NT), 0, s, a, (int)tiles);
+  return hipGetLastError();
+}
+
+}  // namespace convk
+}  // namespace ffv

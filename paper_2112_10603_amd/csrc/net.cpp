@@ -609,8 +609,12 @@ Status Net::conv(const Exec& x, const Layer& L, const void* in, int in_ld, long 
   a.tile_w = conv_tile_width(a.Ho, a.Wo);
   ConvTile tile = L.tile;
   const DType kdt = in_fp8 ? DType::FP8 : dt_;
-  // few output channels over a stride-1 3x3 neighbourhood: the halo kernel
-  if (L.rows <= 32 && conv_halo_ok(kdt, a)) {
+  // few output channels over a stride-1 3x3 neighbourhood: the persistent
+  // kernel with resident weights where they fit, else the halo kernel
+  if (L.rows <= 64 && conv_resident_ok(kdt, a, L.rows <= 32 ? 32 : 64)) {
+    tile = L.rows <= 32 ? ConvTile::R32 : ConvTile::R64;
+    a.tile_w = 16;
+  } else if (L.rows <= 32 && conv_halo_ok(kdt, a)) {
     tile = ConvTile::H32;
     a.tile_w = 16;
   }
@@ -1191,8 +1195,9 @@ Status Net::autotune(const float* const* left, const float* const* right, int n_
   FFV_TRY(check(hipEventCreate(&e0), "hipEventCreate"));
   Status res = check(hipEventCreate(&e1), "hipEventCreate");
   std::map<TuneKey, TuneVal> found;
-  const ConvTile tiles[5] = {ConvTile::N256, ConvTile::N128, ConvTile::N64, ConvTile::N32,
-                             ConvTile::H32};
+  const ConvTile tiles[9] = {ConvTile::N256, ConvTile::N128, ConvTile::N64,
+                             ConvTile::N32,  ConvTile::H32,  ConvTile::H256,
+                             ConvTile::H128, ConvTile::R32,  ConvTile::R64};
   const int widths[4] = {8, 16, 32, 64};
   for (size_t r = 0; res.good() && r < recs_.size(); ++r) {
     const TuneRec& rec = recs_[r];
@@ -1206,18 +1211,22 @@ Status Net::autotune(const float* const* left, const float* const* right, int n_
     }
     float best_ms = -1.f;
     TuneVal best{};
-    for (int ti = 0; res.good() && ti < 5; ++ti) {
-      const bool halo = tiles[ti] == ConvTile::H32;
-      const int bn = halo ? 32 : 256 >> ti;
+    for (int ti = 0; res.good() && ti < 9; ++ti) {
+      const bool resident = tiles[ti] == ConvTile::R32 || tiles[ti] == ConvTile::R64;
+      const bool halo = tiles[ti] == ConvTile::H32 || resident;
+      const bool halo_big = tiles[ti] == ConvTile::H256 || tiles[ti] == ConvTile::H128;
+      const int bn = conv_tile_bn(tiles[ti]);
       if (bn >= 2 * rows32) continue;  // at least half of every tile's columns real
-      if (halo && !conv_halo_ok(rec.dt, rec.a)) continue;
+      if (tiles[ti] == ConvTile::H32 && !conv_halo_ok(rec.dt, rec.a)) continue;
+      if (resident && !conv_resident_ok(rec.dt, rec.a, bn)) continue;
       for (int tw : widths) {
-        if (halo && tw != 16) continue;  // the halo kernel's block is 16 x 16
+        if (halo && tw != 16) continue;  // the halo kernels' block is 16 x 16
         const int th = 256 / tw;
         const long area = (long)((rec.a.Ho + th - 1) / th) * th * ((rec.a.Wo + tw - 1) / tw) * tw;
         if (!halo && area * 10 > min_area * 11) continue;  // within 10 % of the least padding
         ConvArgs a = rec.a;
         a.tile_w = tw;
+        if (halo_big && !conv_halo_tile_ok(rec.dt, a)) continue;
         a.amax = nullptr;
         res = check(launch_conv(rec.dt, tiles[ti], a, stream_), "autotune warm-up");
         if (!res.good()) break;
@@ -1251,7 +1260,9 @@ Status Net::autotune(const float* const* left, const float* const* right, int n_
 }
 
 static std::string tile_name(ConvTile t) {
-  return t == ConvTile::H32 ? std::string("h32") : std::to_string(256 >> (int)t);
+  const std::string n = std::to_string(conv_tile_bn(t));
+  if (t == ConvTile::R32 || t == ConvTile::R64) return "r" + n;
+  return (t == ConvTile::H32 || t == ConvTile::H256 || t == ConvTile::H128) ? "h" + n : n;
 }
 
 Status Net::save_tuning(const std::string& path) {
@@ -1293,11 +1304,15 @@ Status Net::load_tuning(const std::string& path, int* n_loaded) {
     else if (tn == "64") t = ConvTile::N64;
     else if (tn == "32") t = ConvTile::N32;
     else if (tn == "h32" && tw == 16) t = ConvTile::H32;
+    else if (tn == "h256" && (tw == 8 || tw == 16 || tw == 32)) t = ConvTile::H256;
+    else if (tn == "h128" && (tw == 8 || tw == 16 || tw == 32)) t = ConvTile::H128;
+    else if (tn == "r32" && tw == 16) t = ConvTile::R32;
+    else if (tn == "r64" && tw == 16) t = ConvTile::R64;
     else {
       st = Status::err(-1, path + ": bad tile on line " + std::to_string(lineno));
       break;
     }
-    const int bn = t == ConvTile::H32 ? 32 : 256 >> (int)t;
+    const int bn = conv_tile_bn(t);
     const Layer& L = layers_.at(name);
     if (L.name == "unet.head" || bn > L.cout_pad) {
       st = Status::err(-1, path + ": entry on line " + std::to_string(lineno) + " does not fit its layer");

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_PKG, "lib", "libffv.so")
 FFV_ABI_VERSION = 1
 FFV_FP32, FFV_BF16, FFV_FP8_E4M3 = 0, 1, 2
 PRECISIONS = {"fp32": FFV_FP32, "bf16": FFV_BF16, "fp8": FFV_FP8_E4M3}
+FFV_OP_ACT_OUT = 0x100  # op_conv: output in the activation dtype
 
 STATUS = {0: "FFV_OK", 1: "FFV_PENDING", -1: "FFV_ERR_ARG", -2: "FFV_ERR_OOM",
           -3: "FFV_ERR_BUDGET", -4: "FFV_ERR_DEVICE", -5: "FFV_ERR_WEIGHTS",
@@ -311,11 +312,12 @@ class Net:
 
 def op_conv(x: torch.Tensor, weight, bias, stride: int = 1, transposed: bool = False,
             relu: bool = False, precision: str = "fp32", n_tile: int = 0,
-            tile_w: int = 0) -> torch.Tensor:
+            tile_w: int = 0, act_out: bool = False) -> torch.Tensor:
     """One conv layer through the library's implicit-GEMM kernel.
     ``x``: [n, cin, h, w] float32 CUDA; ``weight``/``bias``: host arrays in
     the weights-file layout; ``n_tile``/``tile_w``: kernel variant (0 =
-    default)."""
+    default); ``act_out``: the layer writes activation-dtype output, as in
+    the network, returned widened to float32."""
     import numpy as np
     _dev_f32(x, "x")
     n, cin, h, w = x.shape
@@ -328,7 +330,7 @@ def op_conv(x: torch.Tensor, weight, bias, stride: int = 1, transposed: bool = F
         ho, wo = (h - 1) // stride + 1, (w - 1) // stride + 1
     y = torch.empty((n, cout, ho, wo), dtype=torch.float32, device=x.device)
     s = torch.cuda.current_stream(x.device)
-    _check(lib().ffv_op_conv(PRECISIONS[precision], x.data_ptr(), n, cin, h, w,
+    _check(lib().ffv_op_conv(PRECISIONS[precision] | (FFV_OP_ACT_OUT if act_out else 0), x.data_ptr(), n, cin, h, w,
                              wt.ctypes.data, bs.ctypes.data, cout, stride, 1 if transposed else 0,
                              1 if relu else 0, n_tile, tile_w, y.data_ptr(), s.cuda_stream))
     return y

@@ -71,12 +71,29 @@ def test_conv_kernel_vs_oracle(cin, cout, h, w, stride, transposed, precision):
     assert np.all(err <= bound), (err.max(), (err / (absref + 1e-12)).max())
 
 
+def _resident_fits(cin, cout, bn, transposed, stride, elem):
+    """Whether the resident-weight kernel runs the layer: a stride-1 or
+    phase-merged (transposed, at most 16 outputs) 3x3 neighbourhood, whole K
+    steps of channels, at most bn GEMM columns and weights that fit its LDS
+    buffer."""
+    merged = transposed and cout <= 16
+    if not ((not transposed and stride == 1) or merged):
+        return False
+    rows = 4 * cout if merged else cout
+    cin_pad = (cin + 7) // 8 * 8
+    if cin_pad % (128 // elem) or rows > bn:
+        return False
+    return bn * (9 * cin_pad * elem // 16 + 1) <= 4800
+
+
 VARIANT_CASES = [
     # (cin, cout, h, w, stride, transposed): shapes that span several M tiles
     (64, 256, 40, 52, 1, False),
     (128, 128, 37, 45, 2, False),
     (256, 128, 19, 23, 0, True),
     (64, 16, 21, 27, 0, True),
+    (64, 40, 33, 29, 1, False),
+    (128, 5, 18, 35, 0, True),
 ]
 
 
@@ -116,6 +133,17 @@ def test_conv_tile_variants_agree(cin, cout, h, w, stride, transposed):
         got = op_conv(xd, wt, b, stride=max(stride, 1), transposed=transposed, relu=True,
                       precision="bf16", n_tile=1).cpu()
         assert torch.equal(got, base), ("halo", (got - base).abs().max().item())
+    for code, bn in ((4, 32), (5, 64)):  # resident-weight kernels, where they apply
+        if _resident_fits(cin, cout, bn, transposed, stride, 2):
+            got = op_conv(xd, wt, b, stride=max(stride, 1), transposed=transposed, relu=True,
+                          precision="bf16", n_tile=code).cpu()
+            assert torch.equal(got, base), ("resident", bn, (got - base).abs().max().item())
+    if (transposed or stride == 1) and cin % 64 == 0:
+        for code in (2, 3):  # 128- and 256-channel halo tiles
+            for tile_w in (8, 16, 32):
+                got = op_conv(xd, wt, b, stride=max(stride, 1), transposed=transposed, relu=True,
+                              precision="bf16", n_tile=code, tile_w=tile_w).cpu()
+                assert torch.equal(got, base), ("halo tile", code, tile_w, (got - base).abs().max().item())
 
 
 HALO_CASES = [
@@ -158,3 +186,172 @@ def test_conv_halo_kernel_vs_oracle(cin, cout, h, w, transposed, precision):
                   n_tile=1).cpu().numpy()
     err = np.abs(got.astype(np.float64) - ref)
     assert np.all(err <= 2e-5 * absref + 1e-6), (err.max(), (err / (absref + 1e-12)).max())
+
+
+HALO_TILE_CASES = [
+    # (cin, cout, h, w, transposed): the 128/256-channel halo tiles on
+    # stride-1 convs, per-phase transposed convs (cout > 16) and
+    # phase-merged ones (cout <= 16), ragged against every block shape
+    (256, 256, 19, 37, False),
+    (64, 128, 33, 21, False),
+    (128, 200, 9, 70, False),
+    (256, 128, 13, 22, True),
+    (128, 5, 23, 19, True),
+]
+
+
+@pytest.mark.parametrize("cin,cout,h,w,transposed", HALO_TILE_CASES)
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_conv_halo_tiles_vs_oracle(cin, cout, h, w, transposed, precision):
+    """The conv kernel's halo variant (one (TH+2) x (TW+2) input halo per
+    channel slice, every tap read from LDS) against the oracle, for both N
+    tiles and the three block widths it accepts."""
+    from paper_2112_10603_amd import op_conv
+    rng = np.random.default_rng(cin * 13 + cout + h)
+    n = 2
+    x = rng.standard_normal((n, cin, h, w)).astype(np.float32)
+    if transposed:
+        wt = (rng.standard_normal((cin, cout, 4, 4)) / np.sqrt(4 * cin)).astype(np.float32)
+    else:
+        wt = (rng.standard_normal((cout, cin, 3, 3)) / np.sqrt(9 * cin)).astype(np.float32)
+    b = rng.standard_normal(cout).astype(np.float32)
+    if precision == "bf16":
+        xr = torch.from_numpy(x).bfloat16().double().numpy()
+        wr = torch.from_numpy(wt).bfloat16().double().numpy()
+    else:
+        xr, wr = x.astype(np.float64), wt.astype(np.float64)
+    ref = _ref(xr, wr, b.astype(np.float64), 1, transposed, True)
+    absref = _ref(np.abs(xr), np.abs(wr), np.abs(b).astype(np.float64), 1, transposed, False)
+    xd = torch.from_numpy(x).cuda()
+    for code in (2, 3):
+        for tile_w in (8, 16, 32):
+            print(f"case halo tile {code} tw={tile_w} cin={cin} cout={cout} h={h} w={w} T={transposed} "
+                  f"{precision}", flush=True)
+            got = op_conv(xd, wt, b, stride=1, transposed=transposed, relu=True, precision=precision,
+                          n_tile=code, tile_w=tile_w).cpu().numpy()
+            err = np.abs(got.astype(np.float64) - ref)
+            assert np.all(err <= 2e-5 * absref + 1e-6), (code, tile_w, err.max())
+
+
+def test_conv_halo_tile_rejects_other_layers():
+    """A stride-2 conv, or a block width whose halo would not fit, is
+    refused with an error (nothing is launched)."""
+    from paper_2112_10603_amd import op_conv
+    from paper_2112_10603_amd.ffv import FfvError
+    print("case halo tile rejects", flush=True)
+    rng = np.random.default_rng(5)
+    x = torch.from_numpy(rng.standard_normal((1, 64, 12, 12)).astype(np.float32)).cuda()
+    wt = rng.standard_normal((64, 64, 3, 3)).astype(np.float32)
+    b = np.zeros(64, np.float32)
+    with pytest.raises(FfvError):
+        op_conv(x, wt, b, stride=2, precision="bf16", n_tile=3, tile_w=16)
+    with pytest.raises(FfvError):
+        op_conv(x, wt, b, stride=1, precision="bf16", n_tile=3, tile_w=64)
+
+
+RESIDENT_CASES = [
+    # (n, cin, cout, h, w, transposed): the resident-weight kernels on
+    # stride-1 convs and phase-merged transposed convs; the last two have
+    # more 16x16 blocks than workgroups, so each workgroup walks several
+    (2, 64, 16, 37, 45, False),
+    (2, 64, 40, 16, 16, False),
+    (3, 128, 5, 23, 19, True),
+    (2, 64, 16, 17, 31, True),
+    (8, 64, 16, 128, 160, False),
+    (6, 128, 5, 100, 90, True),
+]
+
+
+@pytest.mark.parametrize("n,cin,cout,h,w,transposed", RESIDENT_CASES)
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_conv_resident_vs_oracle(n, cin, cout, h, w, transposed, precision):
+    """The persistent resident-weight kernel against the oracle, for every
+    N tile whose weights fit; bf16 results also equal the default tiling's
+    bit for bit."""
+    from paper_2112_10603_amd import op_conv
+    elem = 2 if precision == "bf16" else 4
+    codes = [code for code, bn in ((4, 32), (5, 64)) if _resident_fits(cin, cout, bn, transposed, 1, elem)]
+    if not codes:
+        pytest.skip("weights do not fit the resident buffer at this precision")
+    rng = np.random.default_rng(n * 101 + cin + cout + h)
+    x = rng.standard_normal((n, cin, h, w)).astype(np.float32)
+    if transposed:
+        wt = (rng.standard_normal((cin, cout, 4, 4)) / np.sqrt(4 * cin)).astype(np.float32)
+    else:
+        wt = (rng.standard_normal((cout, cin, 3, 3)) / np.sqrt(9 * cin)).astype(np.float32)
+    b = rng.standard_normal(cout).astype(np.float32)
+    if precision == "bf16":
+        xr = torch.from_numpy(x).bfloat16().double().numpy()
+        wr = torch.from_numpy(wt).bfloat16().double().numpy()
+    else:
+        xr, wr = x.astype(np.float64), wt.astype(np.float64)
+    ref = _ref(xr, wr, b.astype(np.float64), 1, transposed, True)
+    absref = _ref(np.abs(xr), np.abs(wr), np.abs(b).astype(np.float64), 1, transposed, False)
+    xd = torch.from_numpy(x).cuda()
+    base = op_conv(xd, wt, b, stride=1, transposed=transposed, relu=True, precision=precision).cpu()
+    for code in codes:
+        print(f"case resident {code} n={n} cin={cin} cout={cout} h={h} w={w} T={transposed} {precision}",
+              flush=True)
+        got = op_conv(xd, wt, b, stride=1, transposed=transposed, relu=True, precision=precision,
+                      n_tile=code).cpu()
+        err = np.abs(got.numpy().astype(np.float64) - ref)
+        assert np.all(err <= 2e-5 * absref + 1e-6), (code, err.max())
+        if precision == "bf16":
+            assert torch.equal(got, base), (code, (got - base).abs().max().item())
+
+
+def test_conv_resident_rejects_large_weights():
+    """Weights that do not fit the resident buffer (256 input channels at 32
+    columns), or a stride-2 conv, are refused with an error."""
+    from paper_2112_10603_amd import op_conv
+    from paper_2112_10603_amd.ffv import FfvError
+    print("case resident rejects", flush=True)
+    rng = np.random.default_rng(9)
+    x = torch.from_numpy(rng.standard_normal((1, 256, 16, 16)).astype(np.float32)).cuda()
+    wt = rng.standard_normal((16, 256, 3, 3)).astype(np.float32)
+    b = np.zeros(16, np.float32)
+    with pytest.raises(FfvError):
+        op_conv(x, wt, b, stride=1, precision="bf16", n_tile=4)
+    x2 = torch.from_numpy(rng.standard_normal((1, 64, 16, 16)).astype(np.float32)).cuda()
+    w2 = rng.standard_normal((16, 64, 3, 3)).astype(np.float32)
+    with pytest.raises(FfvError):
+        op_conv(x2, w2, b, stride=2, precision="bf16", n_tile=4)
+
+
+STAGED_CASES = [
+    # (n, cin, cout, h, w, stride, transposed, n_tile, tile_w): layers whose
+    # bf16 output the kernels stage through LDS for 16-byte stores
+    (2, 64, 256, 21, 35, 1, False, 256, 16),
+    (2, 128, 128, 19, 23, 2, False, 128, 32),
+    (2, 256, 128, 9, 13, 0, True, 128, 16),
+    (2, 256, 256, 19, 37, 1, False, 3, 32),
+    (2, 256, 128, 13, 22, 0, True, 2, 16),
+    (2, 64, 16, 37, 45, 1, False, 4, 16),
+    (2, 64, 64, 30, 50, 1, False, 5, 16),
+    (2, 64, 16, 17, 31, 0, True, 5, 16),
+    (8, 64, 16, 128, 160, 1, False, 5, 16),
+    (6, 64, 8, 60, 70, 0, True, 4, 16),
+]
+
+
+@pytest.mark.parametrize("n,cin,cout,h,w,stride,transposed,n_tile,tile_w", STAGED_CASES)
+def test_conv_bf16_output_epilogues(n, cin, cout, h, w, stride, transposed, n_tile, tile_w):
+    """bf16 outputs as the network's layers write them (the LDS-staged
+    16-byte-store epilogues): equal to the float32 output of the same
+    variant rounded to bf16, for every layer kind and tile."""
+    from paper_2112_10603_amd import op_conv
+    print(f"case bf16 out n={n} cin={cin} cout={cout} h={h} w={w} s={stride} T={transposed} "
+          f"tile={n_tile}/{tile_w}", flush=True)
+    rng = np.random.default_rng(cin * 7 + cout + h * 3 + n_tile)
+    x = rng.standard_normal((n, cin, h, w)).astype(np.float32)
+    if transposed:
+        wt = (rng.standard_normal((cin, cout, 4, 4)) / np.sqrt(4 * cin)).astype(np.float32)
+    else:
+        wt = (rng.standard_normal((cout, cin, 3, 3)) / np.sqrt(9 * cin)).astype(np.float32)
+    b = rng.standard_normal(cout).astype(np.float32)
+    xd = torch.from_numpy(x).cuda()
+    kw = dict(stride=max(stride, 1), transposed=transposed, relu=True, precision="bf16",
+              n_tile=n_tile, tile_w=tile_w)
+    f32 = op_conv(xd, wt, b, **kw).cpu()
+    got = op_conv(xd, wt, b, act_out=True, **kw).cpu()
+    assert torch.equal(got, f32.bfloat16().float()), (got - f32.bfloat16().float()).abs().max().item()
