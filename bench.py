@@ -36,7 +36,8 @@ PEAK_HBM_GBS = 8000.0
 
 
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "conv_igemm_dense1080p_bf16_hbm_counters.md")
-CONV_SOURCES = [os.path.join(ROOT, "paper_2112_10603_amd", "csrc", f) for f in ("conv_kernel.h", "conv.hip")]
+CONV_SOURCES = [os.path.join(ROOT, "paper_2112_10603_amd", "csrc", f)
+                for f in ("conv_kernel.h", "conv_halo.h", "conv_resident.h", "conv.hip")]
 
 
 def measured_traffic():

@@ -420,17 +420,56 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   // (vmcnt drains in issue order).
   if constexpr (HALO) {
     // two weight stages and two halo buffers; every load of step kc is
-    // waited for (vmcnt 0) before the barrier of step kc + 1
+    // waited for (vmcnt 0) before the barrier of step kc + 1. Inside a step
+    // the fragments of round r + 1 are read while round r's MFMAs run, and
+    // the first round's reads go out before the next step's loads are
+    // issued, so the MFMAs start as early as the data allows.
     const int n_slices = a.cin_pad / BK;
+    constexpr int RCH = sizeof(T) == 1 ? 2 : 1;  // chunks per MFMA round
+    constexpr int NR = CH / 2 / RCH;              // rounds per step
     issue_b(0, 0);
     if (n_slices > 0) issue_halo(0, 0, -1);
     for (int kc = 0; kc < nk; ++kc) {
       wait_vm<0>();
       __syncthreads();
       const int slice = kc / a.taps, tap = kc - slice * a.taps;
+      const int buf = kc & 1, abuf = slice & 1;
+      const int hoff = tap_dy(tap) * hwid + tap_dx(tap);
+      uint4 fa[2][FM][RCH], fb[2][FN][RCH];
+      auto read_round = [&](int r, uint4 (&xa)[FM][RCH], uint4 (&xb)[FN][RCH]) {
+#pragma unroll
+        for (int c = 0; c < RCH; ++c) {
+          const int ch = lhalf * (CH / 2) + r * RCH + c;
+#pragma unroll
+          for (int i = 0; i < FM; ++i) xa[i][c] = As[abuf][C::swz(arow(i, hoff), ch)];
+#pragma unroll
+          for (int j = 0; j < FN; ++j) xb[j][c] = Bs[buf][C::swz(wn * TN + j * 32 + lrow, ch)];
+        }
+      };
+      read_round(0, fa[0], fb[0]);
       if (kc + 1 < nk) issue_b(kc + 1, (kc + 1) & 1);
       if (slice + 1 < n_slices) issue_halo(slice + 1, (slice + 1) & 1, tap);
-      compute(kc & 1, slice & 1, tap_dy(tap) * hwid + tap_dx(tap));
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int cur = r & 1;
+        if (r + 1 < NR) read_round(r + 1, fa[cur ^ 1], fb[cur ^ 1]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            if constexpr (sizeof(T) == 1) {
+              if constexpr (SW)
+                mfma_f8(acc[i][j], fb[cur][j][0], fb[cur][j][1], fa[cur][i][0], fa[cur][i][1]);
+              else
+                mfma_f8(acc[i][j], fa[cur][i][0], fa[cur][i][1], fb[cur][j][0], fb[cur][j][1]);
+            } else {
+              if constexpr (SW)
+                mfma_chunk<T>(acc[i][j], fb[cur][j][0], fa[cur][i][0]);
+              else
+                mfma_chunk<T>(acc[i][j], fa[cur][i][0], fb[cur][j][0]);
+            }
+          }
+      }
     }
   } else {
     constexpr int LPS = A_IT + B_IT;  // loads per step per thread

@@ -52,14 +52,18 @@ inline bool resident_ok(const ConvArgs& a, int bn, int elem_bytes) {
 }
 
 // Two waves per SIMD is all the LDS footprint allows; saying so lets the
-// compiler keep a second tap's fragments in registers. SW: the weights are
-// the MFMA's A operand, so a lane ends with runs of 4 consecutive output
-// channels of one pixel, and the epilogue stages each wave's 32 x BN output
-// tile through LDS for 16-byte stores (bf16/fp8 outputs in 16-byte channel
-// runs); otherwise lanes store single values from registers.
-template <typename T, int BN, bool SW>
+// compiler keep a second tap's fragments in registers. EPI 1 and 2: the
+// weights are the MFMA's A operand, so a lane ends with runs of 4
+// consecutive GEMM columns of one pixel, and the epilogue stages each
+// wave's 32 x BN output tile through LDS: EPI 1 for bf16/fp8 outputs in
+// 16-byte channel runs (16-byte stores), EPI 2 for float outputs of a
+// 32-column tile (one lane per output pixel, float4 accesses, in-place
+// accumulation). EPI 0: lanes store single values from registers.
+template <typename T, int BN, int EPI>
 __global__ __launch_bounds__(Resident::NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void conv_resident(ConvArgs a, int n_tiles) {
+  constexpr bool SW = EPI != 0;
+  static_assert(EPI != 2 || BN == 32, "float staging holds 32-column tiles");
   using R = Resident;
   constexpr int NT = R::NT, CH = R::CH, TW = R::TW, TH = R::TH, HW = R::HW;
   constexpr int A_IT = R::A_IT, A_VECS = R::A_VECS, FN = BN / 32;
@@ -269,6 +273,74 @@ void conv_resident(ConvArgs a, int n_tiles) {
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[f][e] = 0.f;
   };
+  auto epilogue_f32 = [&](int t, int buf) {
+    // as epilogue_staged, with float values: row p of the wave's region
+    // holds the BN GEMM columns of pixel p; then one lane per output pixel
+    // (four per GEMM pixel when phase-merged) gathers its cout values and
+    // writes (or adds) them with float4 accesses where they allow.
+    const int img = t / per_img, rem = t - img * per_img;
+    const int ty0 = (rem / tiles_x) * TH, tx0 = (rem % tiles_x) * TW;
+    constexpr int CPR = BN * 4 / 16;  // 16-byte chunks per staged row
+    float* region = reinterpret_cast<float*>(reinterpret_cast<char*>(&Ah[buf][0]) + wave * 32 * BN * 4);
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f < FN; ++f) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int n0 = f * 32 + 8 * g + 4 * lhalf;
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int n = n0 + q;
+          const bool nok = n < a.n_rows;
+          const int o = nok ? (merged ? n % cout_m : n) : 0;
+          float x = acc[f][4 * g + q] * (a.w_scale ? a.w_scale[o] : 1.f) + a.bias[o];
+          if (a.relu) x = fmaxf(x, 0.f);
+          if (a.amax && nok) atomicMax(reinterpret_cast<unsigned*>(a.amax) + o, __float_as_uint(fabsf(x)));
+          v[q] = x;
+        }
+        *reinterpret_cast<float4*>(region + lrow * BN + (((n0 >> 2) ^ (lrow & (CPR - 1))) << 2)) =
+            make_float4(v[0], v[1], v[2], v[3]);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // own region only: in-order LDS suffices
+    __builtin_amdgcn_wave_barrier();
+    const int nph = merged ? 4 : 1;
+    const int per = merged ? cout_m : a.cout;  // values per output pixel
+    for (int q = lane; q < 32 * nph; q += 64) {
+      const int p = q / nph, ph = q - p * nph;
+      const int row = wave * 32 + p;
+      const int oy = ty0 + row / TW, ox = tx0 + row % TW;
+      if (oy >= a.Ho || ox >= a.Wo) continue;
+      const long pix = merged ? (long)(2 * oy + (ph >> 1)) * a.Wout + 2 * ox + (ph & 1) : (long)oy * a.Wout + ox;
+      float* dst = reinterpret_cast<float*>(a.out) + (long)img * a.out_img_stride + pix * a.out_ld;
+      for (int c0 = 0; c0 < per; c0 += 4) {
+        float v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int col = ph * per + c0 + k;
+          v[k] = (c0 + k < per) ? region[p * BN + (((col >> 2) ^ (p & (CPR - 1))) << 2) + (col & 3)] : 0.f;
+        }
+        if (c0 + 4 <= per) {
+          float4 w = make_float4(v[0], v[1], v[2], v[3]);
+          if (a.accumulate) {
+            const float4 old = *reinterpret_cast<const float4*>(dst + c0);
+            w.x += old.x;
+            w.y += old.y;
+            w.z += old.z;
+            w.w += old.w;
+          }
+          *reinterpret_cast<float4*>(dst + c0) = w;
+        } else {
+          for (int k = 0; c0 + k < per; ++k) dst[c0 + k] = a.accumulate ? dst[c0 + k] + v[k] : v[k];
+        }
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < FN; ++f)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[f][e] = 0.f;
+  };
   // (pixels as A): lane l holds channel f*32 + l%32 of 16 pixels per
   // fragment; registers straight to global memory.
   auto epilogue = [&](int t) {
@@ -331,8 +403,10 @@ void conv_resident(ConvArgs a, int n_tiles) {
         issue_halo(t + t_step, 0, (j + 1) & 1);
       compute(j & 1, s);
     }
-    if constexpr (SW)
+    if constexpr (EPI == 1)
       epilogue_staged(t, (j - 1) & 1);
+    else if constexpr (EPI == 2)
+      epilogue_f32(t, (j - 1) & 1);
     else
       epilogue(t);
   }
@@ -365,16 +439,26 @@ hipError_t launch_resident(const ConvArgs& a, hipStream_t s) {
   const int cus = device_cus();
   const long per_xcd = cus >= 8 ? cus / 8 * 8 : cus;  // one workgroup per compute unit
   const int grid = (int)(tiles < per_xcd ? tiles : per_xcd);
-  // the staged epilogue needs bf16/fp8 outputs in 16-byte channel runs
+  // staged epilogues: bf16/fp8 outputs in 16-byte channel runs, or float
+  // outputs of a 32-column tile in 16-byte aligned pixels
   const int run = a.out_scale ? 16 : 8;
-  const bool staged = sizeof(T) != 4 && !a.out_f32 && a.cout % run == 0 && a.out_ld % run == 0;
+  const bool out16 = ((uintptr_t)a.out & 15) == 0;
+  const bool staged16 = sizeof(T) != 4 && !a.out_f32 && a.cout % run == 0 && a.out_ld % run == 0 &&
+                        a.out_img_stride % run == 0 && out16;
+  const bool staged32 = BN == 32 && a.out_f32 && a.out_ld % 4 == 0 && a.out_img_stride % 4 == 0 && out16;
   if constexpr (sizeof(T) != 4) {
-    if (staged) {
-      hipLaunchKernelGGL((conv_resident<T, BN, true>), dim3(grid), dim3(Resident::NT), 0, s, a, (int)tiles);
+    if (staged16) {
+      hipLaunchKernelGGL((conv_resident<T, BN, 1>), dim3(grid), dim3(Resident::NT), 0, s, a, (int)tiles);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((conv_resident<T, BN, false>), dim3(grid), dim3(Resident::NT), 0, s, a, (int)tiles);
+  if constexpr (BN == 32) {
+    if (staged32) {
+      hipLaunchKernelGGL((conv_resident<T, BN, 2>), dim3(grid), dim3(Resident::NT), 0, s, a, (int)tiles);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((conv_resident<T, BN, 0>), dim3(grid), dim3(Resident::NT), 0, s, a, (int)tiles);
   return hipGetLastError();
 }
 
