@@ -133,8 +133,8 @@ ffv_status ffv_interpolate_recursive(ffv_net* net, const ffv_pair* views, int32_
 /*
  * Conv tile autotuning (the conv kernel is instantiated for 256-pixel M tiles
  * with 256/128/64/32-channel N tiles, halo variants with 256/128/32
- * channels and resident-weight variants with 64/32; the 256 pixels form a
- * tile_w-wide 2-D block). Runs the call exactly as ffv_interpolate does (same arguments, same
+ * channels, resident-weight variants with 64/32 and stride-2 resident
+ * variants with 128/64/32; the 256 pixels form a tile_w-wide 2-D block). Runs the call exactly as ffv_interpolate does (same arguments, same
  * result in *out*), then re-launches each convolution of that call with
  * every candidate (N tile at most twice the real channel count rounded to
  * 32; pixel-block widths 8, 16, 32, 64 within 10 % of the least padding),
@@ -150,8 +150,8 @@ ffv_status ffv_autotune(ffv_net* net, const ffv_pair* views, int32_t n_pairs, co
 /*
  * Tuning table as text, one line per launch shape:
  * "layer fp8 Ho Wo n_img n_tile tile_w" ('#' starts a comment line); n_tile
- * is 256, 128, 64, 32, or h256, h128, h32 for the halo variants, or r64, r32
- * for the resident-weight variants.
+ * is 256, 128, 64, 32, or h256, h128, h32 for the halo variants, r64, r32
+ * for the resident-weight variants, s128, s64, s32 for the stride-2 ones.
  * ffv_save_tuning writes the net's table; ffv_load_tuning merges a file's
  * entries into it (*n_loaded, nullable, = entries read) and rejects the
  * whole file on a malformed line, an unknown layer or a tile that does not
@@ -301,8 +301,11 @@ ffv_status ffv_stitch_cluster(const float* real_view, const float* const* left,
  * transposed convs whose input channels are a multiple of the K step, with
  * tile_w 8, 16 or 32; 4 and 5 = the persistent kernel with the layer's
  * weights resident in LDS, 32 or 64 GEMM columns, for stride-1 and
- * phase-merged transposed convs with few output channels; a variant that
- * cannot run the layer gives FFV_ERR_DEVICE) and tile_w (0 = default, else the
+ * phase-merged transposed convs with few output channels; 6, 7, 8 = the
+ * persistent stride-2 kernel for 8 to 32 input channels with 32, 64 or 128
+ * columns, weights resident, bf16 outputs in 16-byte channel runs only; a
+ * variant that cannot run the layer gives FFV_ERR_DEVICE) and tile_w (0 =
+ * default, else the
  * width of the 256-pixel block of a workgroup, a divisor of 256) pick the
  * kernel variant, as autotuning does; every choice gives the same result.
  * Allocates temporaries; synchronises `stream`.

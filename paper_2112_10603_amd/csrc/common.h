@@ -69,14 +69,17 @@ struct ConvArgs {
 // neighbourhoods and per-phase transposed convs; M-tile width 8, 16 or 32);
 // R32, R64: the persistent halo kernel with the layer's weights resident in
 // LDS (stride-1 3x3 neighbourhoods with at most 32/64 GEMM columns and small
-// weights; M-tile width 16).
-enum class ConvTile : int { N256 = 0, N128 = 1, N64 = 2, N32 = 3, H32 = 4, H256 = 5, H128 = 6, R32 = 7, R64 = 8 };
+// weights; M-tile width 16); S32, S64, S128: the persistent stride-2 kernel
+// for 8 to 32 input channels, weights resident (M-tile width 16).
+enum class ConvTile : int {
+  N256 = 0, N128 = 1, N64 = 2, N32 = 3, H32 = 4, H256 = 5, H128 = 6, R32 = 7, R64 = 8, S32 = 9, S64 = 10, S128 = 11
+};
 // N tile (output channels per workgroup) of a tile kind.
 inline int conv_tile_bn(ConvTile t) {
   switch (t) {
     case ConvTile::N256: case ConvTile::H256: return 256;
-    case ConvTile::N128: case ConvTile::H128: return 128;
-    case ConvTile::N64: case ConvTile::R64: return 64;
+    case ConvTile::N128: case ConvTile::H128: case ConvTile::S128: return 128;
+    case ConvTile::N64: case ConvTile::R64: case ConvTile::S64: return 64;
     default: return 32;
   }
 }
@@ -87,6 +90,9 @@ bool conv_halo_tile_ok(DType dt, const ConvArgs& a);
 // Whether the resident-weight kernel with a bn-channel N tile (32 or 64) can
 // run a launch (tile_w is not checked: the kernel's block is 16 x 16).
 bool conv_resident_ok(DType dt, const ConvArgs& a, int bn);
+// Whether the stride-2 resident kernel with a bn-channel N tile (32, 64 or
+// 128) can run a launch.
+bool conv_resident_s2_ok(DType dt, const ConvArgs& a, int bn);
 
 hipError_t launch_conv(DType dt, ConvTile tile, const ConvArgs& a, hipStream_t s);
 // Width of the 2-D pixel block of a 256-pixel M tile for a Ho x Wo grid:

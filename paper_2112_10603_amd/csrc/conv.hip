@@ -5,10 +5,33 @@
 #include "conv_halo.h"
 #include "conv_kernel.h"
 #include "conv_resident.h"
+#include "conv_resident_s2.h"
 
 namespace ffv {
 
 namespace {
+
+// the stride-2 resident kernel for the (channel chunks, N tile) pairs whose
+// buffers fit LDS
+template <typename T, int PC, int BN>
+hipError_t launch_s2_pc(const ConvArgs& a, hipStream_t s) {
+  if constexpr (convk::ResS2::vecs(PC, BN) <= convk::ResS2::LDS_VECS)
+    return convk::launch_resident_s2<T, PC, BN>(a, s);
+  else
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int BN>
+hipError_t launch_s2(const ConvArgs& a, hipStream_t s) {
+  if (a.cin_pad % 8 != 0) return hipErrorInvalidValue;
+  switch (a.cin_pad / 8) {
+    case 1: return launch_s2_pc<T, 1, BN>(a, s);
+    case 2: return launch_s2_pc<T, 2, BN>(a, s);
+    case 3: return launch_s2_pc<T, 3, BN>(a, s);
+    case 4: return launch_s2_pc<T, 4, BN>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
 
 template <typename T>
 hipError_t launch_t(ConvTile tile, const ConvArgs& a, hipStream_t s) {
@@ -32,6 +55,12 @@ hipError_t launch_t(ConvTile tile, const ConvArgs& a, hipStream_t s) {
       return launch_resident<T, 32>(a, s);
     case ConvTile::R64:
       return launch_resident<T, 64>(a, s);
+    case ConvTile::S32:
+      return launch_s2<T, 32>(a, s);
+    case ConvTile::S64:
+      return launch_s2<T, 64>(a, s);
+    case ConvTile::S128:
+      return launch_s2<T, 128>(a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -46,6 +75,26 @@ bool conv_resident_ok(DType dt, const ConvArgs& a, int bn) {
   ConvArgs b = a;
   b.tile_w = convk::Resident::TW;
   return convk::resident_ok(b, bn, (int)dtype_size(dt));
+}
+
+bool conv_resident_s2_ok(DType dt, const ConvArgs& a, int bn) {
+  if (a.cin_pad % 8 != 0 || a.cin_pad < 8 || a.cin_pad > 32) return false;
+  const int pc = a.cin_pad / 8;
+  static constexpr int fits[5][3] = {{0, 0, 0},
+                                     {convk::ResS2::vecs(1, 32) <= convk::ResS2::LDS_VECS,
+                                      convk::ResS2::vecs(1, 64) <= convk::ResS2::LDS_VECS,
+                                      convk::ResS2::vecs(1, 128) <= convk::ResS2::LDS_VECS},
+                                     {convk::ResS2::vecs(2, 32) <= convk::ResS2::LDS_VECS,
+                                      convk::ResS2::vecs(2, 64) <= convk::ResS2::LDS_VECS,
+                                      convk::ResS2::vecs(2, 128) <= convk::ResS2::LDS_VECS},
+                                     {convk::ResS2::vecs(3, 32) <= convk::ResS2::LDS_VECS,
+                                      convk::ResS2::vecs(3, 64) <= convk::ResS2::LDS_VECS,
+                                      convk::ResS2::vecs(3, 128) <= convk::ResS2::LDS_VECS},
+                                     {convk::ResS2::vecs(4, 32) <= convk::ResS2::LDS_VECS,
+                                      convk::ResS2::vecs(4, 64) <= convk::ResS2::LDS_VECS,
+                                      convk::ResS2::vecs(4, 128) <= convk::ResS2::LDS_VECS}};
+  const int bi = bn == 32 ? 0 : (bn == 64 ? 1 : (bn == 128 ? 2 : -1));
+  return bi >= 0 && fits[pc][bi] && convk::resident_s2_ok(a, pc, bn, (int)dtype_size(dt));
 }
 
 bool conv_halo_ok(DType dt, const ConvArgs& a) {

@@ -617,6 +617,14 @@ Status Net::conv(const Exec& x, const Layer& L, const void* in, int in_ld, long 
   } else if (L.rows <= 32 && conv_halo_ok(kdt, a)) {
     tile = ConvTile::H32;
     a.tile_w = 16;
+  } else if (L.stride == 2 && !L.transposed && !out_f32 && L.rows <= 128) {
+    // stride-2 convs over a few input channels: the persistent stride-2
+    // kernel with resident weights, narrowest N tile that holds the layer
+    const int bn = L.rows <= 32 ? 32 : (L.rows <= 64 ? 64 : 128);
+    if (conv_resident_s2_ok(kdt, a, bn)) {
+      tile = bn == 32 ? ConvTile::S32 : (bn == 64 ? ConvTile::S64 : ConvTile::S128);
+      a.tile_w = 16;
+    }
   }
   if (!tuned_.empty() || recording_) {
     const TuneKey key{L.name, in_fp8 ? 1 : 0, a.Ho, a.Wo, n_img};
@@ -1195,9 +1203,9 @@ Status Net::autotune(const float* const* left, const float* const* right, int n_
   FFV_TRY(check(hipEventCreate(&e0), "hipEventCreate"));
   Status res = check(hipEventCreate(&e1), "hipEventCreate");
   std::map<TuneKey, TuneVal> found;
-  const ConvTile tiles[9] = {ConvTile::N256, ConvTile::N128, ConvTile::N64,
-                             ConvTile::N32,  ConvTile::H32,  ConvTile::H256,
-                             ConvTile::H128, ConvTile::R32,  ConvTile::R64};
+  const ConvTile tiles[12] = {ConvTile::N256, ConvTile::N128, ConvTile::N64, ConvTile::N32,
+                              ConvTile::H32,  ConvTile::H256, ConvTile::H128, ConvTile::R32,
+                              ConvTile::R64,  ConvTile::S32,  ConvTile::S64,  ConvTile::S128};
   const int widths[4] = {8, 16, 32, 64};
   for (size_t r = 0; res.good() && r < recs_.size(); ++r) {
     const TuneRec& rec = recs_[r];
@@ -1211,14 +1219,16 @@ Status Net::autotune(const float* const* left, const float* const* right, int n_
     }
     float best_ms = -1.f;
     TuneVal best{};
-    for (int ti = 0; res.good() && ti < 9; ++ti) {
+    for (int ti = 0; res.good() && ti < 12; ++ti) {
       const bool resident = tiles[ti] == ConvTile::R32 || tiles[ti] == ConvTile::R64;
-      const bool halo = tiles[ti] == ConvTile::H32 || resident;
+      const bool s2 = tiles[ti] == ConvTile::S32 || tiles[ti] == ConvTile::S64 || tiles[ti] == ConvTile::S128;
+      const bool halo = tiles[ti] == ConvTile::H32 || resident || s2;
       const bool halo_big = tiles[ti] == ConvTile::H256 || tiles[ti] == ConvTile::H128;
       const int bn = conv_tile_bn(tiles[ti]);
       if (bn >= 2 * rows32) continue;  // at least half of every tile's columns real
       if (tiles[ti] == ConvTile::H32 && !conv_halo_ok(rec.dt, rec.a)) continue;
       if (resident && !conv_resident_ok(rec.dt, rec.a, bn)) continue;
+      if (s2 && !conv_resident_s2_ok(rec.dt, rec.a, bn)) continue;
       for (int tw : widths) {
         if (halo && tw != 16) continue;  // the halo kernels' block is 16 x 16
         const int th = 256 / tw;
@@ -1262,6 +1272,7 @@ Status Net::autotune(const float* const* left, const float* const* right, int n_
 static std::string tile_name(ConvTile t) {
   const std::string n = std::to_string(conv_tile_bn(t));
   if (t == ConvTile::R32 || t == ConvTile::R64) return "r" + n;
+  if (t == ConvTile::S32 || t == ConvTile::S64 || t == ConvTile::S128) return "s" + n;
   return (t == ConvTile::H32 || t == ConvTile::H256 || t == ConvTile::H128) ? "h" + n : n;
 }
 
@@ -1308,6 +1319,9 @@ Status Net::load_tuning(const std::string& path, int* n_loaded) {
     else if (tn == "h128" && (tw == 8 || tw == 16 || tw == 32)) t = ConvTile::H128;
     else if (tn == "r32" && tw == 16) t = ConvTile::R32;
     else if (tn == "r64" && tw == 16) t = ConvTile::R64;
+    else if (tn == "s32" && tw == 16) t = ConvTile::S32;
+    else if (tn == "s64" && tw == 16) t = ConvTile::S64;
+    else if (tn == "s128" && tw == 16) t = ConvTile::S128;
     else {
       st = Status::err(-1, path + ": bad tile on line " + std::to_string(lineno));
       break;
