@@ -11,26 +11,31 @@ namespace ffv {
 
 namespace {
 
-// the stride-2 resident kernel for the (channel chunks, N tile) pairs whose
-// buffers fit LDS
-template <typename T, int PC, int BN>
+// the few-channel resident kernel for the (channel chunks, N tile, stride)
+// triples whose buffers fit LDS
+template <typename T, int PC, int BN, int ST>
 hipError_t launch_s2_pc(const ConvArgs& a, hipStream_t s) {
-  if constexpr (convk::ResS2::vecs(PC, BN) <= convk::ResS2::LDS_VECS)
-    return convk::launch_resident_s2<T, PC, BN>(a, s);
+  if constexpr (convk::ResS2::vecs(PC, BN, ST) <= convk::ResS2::LDS_VECS)
+    return convk::launch_resident_s2<T, PC, BN, ST>(a, s);
   else
     return hipErrorInvalidValue;
 }
 
-template <typename T, int BN>
-hipError_t launch_s2(const ConvArgs& a, hipStream_t s) {
+template <typename T, int BN, int ST>
+hipError_t launch_s2_st(const ConvArgs& a, hipStream_t s) {
   if (a.cin_pad % 8 != 0) return hipErrorInvalidValue;
   switch (a.cin_pad / 8) {
-    case 1: return launch_s2_pc<T, 1, BN>(a, s);
-    case 2: return launch_s2_pc<T, 2, BN>(a, s);
-    case 3: return launch_s2_pc<T, 3, BN>(a, s);
-    case 4: return launch_s2_pc<T, 4, BN>(a, s);
+    case 1: return launch_s2_pc<T, 1, BN, ST>(a, s);
+    case 2: return launch_s2_pc<T, 2, BN, ST>(a, s);
+    case 3: return launch_s2_pc<T, 3, BN, ST>(a, s);
+    case 4: return launch_s2_pc<T, 4, BN, ST>(a, s);
   }
   return hipErrorInvalidValue;
+}
+
+template <typename T, int BN>
+hipError_t launch_s2(const ConvArgs& a, hipStream_t s) {
+  return a.stride == 1 ? launch_s2_st<T, BN, 1>(a, s) : launch_s2_st<T, BN, 2>(a, s);
 }
 
 template <typename T>
@@ -78,23 +83,11 @@ bool conv_resident_ok(DType dt, const ConvArgs& a, int bn) {
 }
 
 bool conv_resident_s2_ok(DType dt, const ConvArgs& a, int bn) {
-  if (a.cin_pad % 8 != 0 || a.cin_pad < 8 || a.cin_pad > 32) return false;
-  const int pc = a.cin_pad / 8;
-  static constexpr int fits[5][3] = {{0, 0, 0},
-                                     {convk::ResS2::vecs(1, 32) <= convk::ResS2::LDS_VECS,
-                                      convk::ResS2::vecs(1, 64) <= convk::ResS2::LDS_VECS,
-                                      convk::ResS2::vecs(1, 128) <= convk::ResS2::LDS_VECS},
-                                     {convk::ResS2::vecs(2, 32) <= convk::ResS2::LDS_VECS,
-                                      convk::ResS2::vecs(2, 64) <= convk::ResS2::LDS_VECS,
-                                      convk::ResS2::vecs(2, 128) <= convk::ResS2::LDS_VECS},
-                                     {convk::ResS2::vecs(3, 32) <= convk::ResS2::LDS_VECS,
-                                      convk::ResS2::vecs(3, 64) <= convk::ResS2::LDS_VECS,
-                                      convk::ResS2::vecs(3, 128) <= convk::ResS2::LDS_VECS},
-                                     {convk::ResS2::vecs(4, 32) <= convk::ResS2::LDS_VECS,
-                                      convk::ResS2::vecs(4, 64) <= convk::ResS2::LDS_VECS,
-                                      convk::ResS2::vecs(4, 128) <= convk::ResS2::LDS_VECS}};
-  const int bi = bn == 32 ? 0 : (bn == 64 ? 1 : (bn == 128 ? 2 : -1));
-  return bi >= 0 && fits[pc][bi] && convk::resident_s2_ok(a, pc, bn, (int)dtype_size(dt));
+  using convk::ResS2;
+  if (a.cin_pad % 8 != 0 || a.cin_pad < 8 || a.cin_pad > 32 || (a.stride != 1 && a.stride != 2)) return false;
+  const int pc = a.cin_pad / 8, st = a.stride;
+  if (bn != 32 && bn != 64 && bn != 128) return false;
+  return ResS2::vecs(pc, bn, st) <= ResS2::LDS_VECS && convk::resident_s2_ok(a, pc, bn, st, (int)dtype_size(dt));
 }
 
 bool conv_halo_ok(DType dt, const ConvArgs& a) {

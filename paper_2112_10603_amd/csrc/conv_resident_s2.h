@@ -1,7 +1,8 @@
-// Persistent stride-2 3x3 convolution for layers with few input channels,
-// with the weights resident in LDS (supplementary layer table: the first
-// conv of each VIBlock, 8 or 24 input channels to 128, and the first convs
-// of the U-Net and context-feature levels, 8 to 32 input channels).
+// Persistent 3x3 convolution (stride 2, or 1) for layers with few input
+// channels, with the weights resident in LDS (supplementary layer table:
+// the first conv of each VIBlock, 8 or 24 input channels to 128, and the
+// convs of the U-Net and context-feature levels with 8 to 32 input
+// channels).
 //
 // The generic kernel gathers these layers' A tiles in 16-byte pieces (one
 // tap's 8 channels of one input pixel per piece), so each input pixel is
@@ -9,13 +10,13 @@
 // two to five 128-byte steps: it spends its time waiting on loads. Here a
 // workgroup stays on its compute unit with the whole weight matrix in LDS
 // and walks output blocks of TH x 16 pixels; per block it loads the input
-// halo, (2 TH + 1) x 33 pixels with all their channels, once, and every tap
-// of every K chunk reads from it. The next block's halo loads into the
-// second buffer while the current one computes. Halo columns are stored by
-// parity (even input columns, then odd), so the 32 pixels of an MFMA
-// fragment read consecutive halo pixels at any tap; the pixel pitch is an
-// odd number of 16-byte chunks, which keeps 16 consecutive pixels in
-// distinct bank groups. K runs tap-major, as the weights of these layers
+// halo, (2 TH + 1) x 33 pixels at stride 2 or (TH + 2) x 18 at stride 1,
+// with all their channels, once, and every tap of every K chunk reads from
+// it. The next block's halo loads into the second buffer while the current
+// one computes. At stride 2 halo columns are stored by parity (even input
+// columns, then odd), so the 32 pixels of an MFMA fragment read consecutive
+// halo pixels at any tap; the pixel pitch is an odd number of 16-byte
+// chunks, which keeps 16 consecutive pixels in distinct bank groups. K runs tap-major, as the weights of these layers
 // are packed: 16-byte chunk q of a K row holds channels 8 (q % PC) .. +7 of
 // tap q / PC, PC = channels / 8.
 #pragma once
@@ -28,9 +29,10 @@ namespace convk {
 struct ResS2 {
   static constexpr int NT = 512;    // 8 waves
   static constexpr int TW = 16;     // output block width
-  static constexpr int HWD = 2 * TW + 1;  // halo width (input columns)
-  static constexpr int HE = TW + 1;       // stored even columns
+  static constexpr int HE = TW + 1;       // stored even columns (stride 2)
   static constexpr int LDS_VECS = 9984;   // 159,744 bytes
+  static constexpr int hwd(int st) { return st == 2 ? 2 * TW + 1 : TW + 2; }  // halo width
+  static constexpr int hh(int st, int th) { return st == 2 ? 2 * th + 1 : th + 2; }  // halo height
   // output block height for an N tile: 8 rows (4 fragments of 32 pixels
   // x 2 column groups) for 64/128 columns, 16 rows for 32
   static constexpr int th(int bn) { return bn >= 64 ? 8 : 16; }
@@ -38,35 +40,36 @@ struct ResS2 {
   static constexpr int kpad(int pc) { return (72 * pc + 63) / 64 * 64; }
   // LDS vectors: two halos, the weights (row pitch one chunk longer than
   // the row), the output staging area (bf16 at most)
-  static constexpr int vecs(int pc, int bn) {
-    return 2 * (2 * th(bn) + 1) * HWD * pp(pc) + bn * (kpad(pc) / 8 + 1) + th(bn) * TW * bn * 2 / 16;
+  static constexpr int vecs(int pc, int bn, int st) {
+    return 2 * hh(st, th(bn)) * hwd(st) * pp(pc) + bn * (kpad(pc) / 8 + 1) + th(bn) * TW * bn * 2 / 16;
   }
 };
 
-// Whether the stride-2 resident kernel with PC 16-byte chunks per input
+// Whether the resident kernel at stride st with PC 16-byte chunks per input
 // pixel (channels = 8 PC) and an N tile of bn columns covers a launch.
-inline bool resident_s2_ok(const ConvArgs& a, int pc, int bn, int elem_bytes) {
-  return elem_bytes == 2 && a.transposed == 0 && a.stride == 2 && a.taps == 9 && a.cin_pad == 8 * pc &&
+inline bool resident_s2_ok(const ConvArgs& a, int pc, int bn, int st, int elem_bytes) {
+  return elem_bytes == 2 && a.transposed == 0 && a.stride == st && a.taps == 9 && a.cin_pad == 8 * pc &&
          a.K == 9 * a.cin_pad && a.K_pad == ResS2::kpad(pc) && a.n_rows <= bn && bn <= a.cout_pad &&
-         a.Ho == (a.Hi - 1) / 2 + 1 && a.Wo == (a.Wi - 1) / 2 + 1 && ResS2::vecs(pc, bn) <= ResS2::LDS_VECS;
+         a.Ho == (a.Hi - 1) / st + 1 && a.Wo == (a.Wi - 1) / st + 1 &&
+         ResS2::vecs(pc, bn, st) <= ResS2::LDS_VECS;
 }
 
-template <typename T, int PC, int BN>
+template <typename T, int PC, int BN, int ST>
 __global__ __launch_bounds__(ResS2::NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void conv_resident_s2(ConvArgs a, int n_tiles) {
   using R = ResS2;
-  constexpr int NT = R::NT, TW = R::TW, HWD = R::HWD, HE = R::HE;
+  constexpr int NT = R::NT, TW = R::TW, HWD = R::hwd(ST), HE = R::HE;
   constexpr int TH = R::th(BN), PP = R::pp(PC), KP = R::kpad(PC);
   constexpr int RC = KP / 8, RCP = RC + 1;  // weight row chunks, pitch
   constexpr int NRD = KP / 16;              // MFMA rounds (two chunks each)
-  constexpr int HV = (2 * TH + 1) * HWD * PP;  // vectors per halo buffer
+  constexpr int HV = R::hh(ST, TH) * HWD * PP;  // vectors per halo buffer
   constexpr int HIT = (HV + NT - 1) / NT;
   constexpr int PG = TH * TW / 32;          // pixel groups (fragments of 32 pixels)
   constexpr int CG = 8 / PG;                // column groups
   constexpr int WC = BN / CG;               // columns per wave
   constexpr int FN = WC / 32;
   static_assert(FN >= 1 && PG * CG == 8, "8 waves of 32-pixel fragments");
-  static_assert(R::vecs(PC, BN) <= R::LDS_VECS, "LDS");
+  static_assert(R::vecs(PC, BN, ST) <= R::LDS_VECS, "LDS");
   constexpr int KQ = 9 * PC;                // real K chunks
 
   __shared__ __attribute__((aligned(16))) uint4 smem[R::LDS_VECS];
@@ -112,13 +115,13 @@ void conv_resident_s2(ConvArgs a, int n_tiles) {
     const int v = tid + i * NT;
     const int hp = v / PP, c = v - hp * PP;
     const int hy = hp / HWD, sc = hp - hy * HWD;
-    const int hx = sc < HE ? 2 * sc : 2 * (sc - HE) + 1;
+    const int hx = ST == 1 ? sc : (sc < HE ? 2 * sc : 2 * (sc - HE) + 1);
     h_yx[i] = (hy << 8) | hx;
     h_c[i] = (v < HV && c < PC) ? c : -1;
   }
   auto issue_halo = [&](int t, int buf) {
     const int img = t / per_img, rem = t - img * per_img;
-    const int iy0 = 2 * ((rem / tiles_x) * TH) - 1, ix0 = 2 * ((rem % tiles_x) * TW) - 1;
+    const int iy0 = ST * ((rem / tiles_x) * TH) - 1, ix0 = ST * ((rem % tiles_x) * TW) - 1;
     const T* src0 = in + (long)img * a.in_img_stride;
 #pragma unroll
     for (int i = 0; i < HIT; ++i) {
@@ -132,12 +135,13 @@ void conv_resident_s2(ConvArgs a, int n_tiles) {
   // this lane's pixel of its fragment, and its halo base (tap (-1, -1))
   const int p = pg * 32 + lrow;
   const int py = p / TW, px = p % TW;
-  // halo row 2 py + dy + 1, stored column: dx = -1 -> px, 0 -> HE + px, +1 -> px + 1
+  // halo row ST py + dy + 1; stored column: at stride 1, px + dx + 1; at
+  // stride 2, dx = -1 -> px, 0 -> HE + px, +1 -> px + 1
   auto a_slot = [&](int q) {  // K chunk q < KQ
     const int tap = q / PC, c = q % PC;
     const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-    const int sc = dx == 0 ? HE + px : px + (dx > 0 ? 1 : 0);
-    return ((2 * py + dy + 1) * HWD + sc) * PP + c;
+    const int sc = ST == 1 ? px + dx + 1 : (dx == 0 ? HE + px : px + (dx > 0 ? 1 : 0));
+    return ((ST * py + dy + 1) * HWD + sc) * PP + c;
   };
   f32x16 acc[FN];
 #pragma unroll
@@ -257,12 +261,12 @@ void conv_resident_s2(ConvArgs a, int n_tiles) {
   wait_vm<0>();
 }
 
-template <typename T, int PC, int BN>
+template <typename T, int PC, int BN, int ST>
 hipError_t launch_resident_s2(const ConvArgs& a, hipStream_t s) {
   if constexpr (sizeof(T) != 2) {
     return hipErrorInvalidValue;
   } else {
-    if (!resident_s2_ok(a, PC, BN, (int)sizeof(T)) || a.n_rows <= 0 || a.in_ld % 8 != 0 ||
+    if (!resident_s2_ok(a, PC, BN, ST, (int)sizeof(T)) || a.n_rows <= 0 || a.in_ld % 8 != 0 ||
         a.in_ld < a.cin_pad)
       return hipErrorInvalidValue;
     // the epilogue stages bf16/fp8 outputs in 16-byte channel runs
@@ -277,7 +281,7 @@ hipError_t launch_resident_s2(const ConvArgs& a, hipStream_t s) {
     const int cus = device_cus();
     const long per_dev = cus >= 8 ? cus / 8 * 8 : cus;
     const int grid = (int)(tiles < per_dev ? tiles : per_dev);
-    hipLaunchKernelGGL((conv_resident_s2<T, PC, BN>), dim3(grid), dim3(ResS2::NT), 0, s, a, (int)tiles);
+    hipLaunchKernelGGL((conv_resident_s2<T, PC, BN, ST>), dim3(grid), dim3(ResS2::NT), 0, s, a, (int)tiles);
     return hipGetLastError();
   }
 }

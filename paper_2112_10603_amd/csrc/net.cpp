@@ -617,9 +617,9 @@ Status Net::conv(const Exec& x, const Layer& L, const void* in, int in_ld, long 
   } else if (L.rows <= 32 && conv_halo_ok(kdt, a)) {
     tile = ConvTile::H32;
     a.tile_w = 16;
-  } else if (L.stride == 2 && !L.transposed && !out_f32 && L.rows <= 128) {
-    // stride-2 convs over a few input channels: the persistent stride-2
-    // kernel with resident weights, narrowest N tile that holds the layer
+  } else if (!L.transposed && !out_f32 && L.rows <= 128) {
+    // convs over a few input channels (8 to 32): the persistent kernel with
+    // resident weights, narrowest N tile that holds the layer
     const int bn = L.rows <= 32 ? 32 : (L.rows <= 64 ? 64 : 128);
     if (conv_resident_s2_ok(kdt, a, bn)) {
       tile = bn == 32 ? ConvTile::S32 : (bn == 64 ? ConvTile::S64 : ConvTile::S128);

@@ -358,50 +358,57 @@ def test_conv_bf16_output_epilogues(n, cin, cout, h, w, stride, transposed, n_ti
 
 
 S2_CASES = [
-    # (n, cin, cout, h, w, n_tile): stride-2 convs with 8 to 32 input channels
-    # (the first conv of a VIBlock, of the U-Net and context levels) through
-    # the persistent stride-2 kernel; odd sizes, and two with more output
+    # (n, cin, cout, h, w, stride, n_tile): convs with 8 to 32 input channels
+    # (the first conv of a VIBlock, the U-Net and context levels) through the
+    # persistent few-channel kernel; odd sizes, and some with more output
     # blocks than workgroups
-    (2, 24, 128, 35, 70, 8),
-    (2, 8, 128, 17, 33, 8),
-    (2, 7, 128, 20, 30, 8),
-    (2, 17, 32, 33, 66, 6),
-    (2, 32, 64, 30, 44, 7),
-    (2, 16, 32, 40, 40, 6),
-    (2, 3, 16, 25, 31, 6),
-    (2, 24, 64, 21, 37, 7),
-    (4, 24, 128, 130, 250, 8),
-    (8, 17, 32, 140, 200, 6),
+    (2, 24, 128, 35, 70, 2, 8),
+    (2, 8, 128, 17, 33, 2, 8),
+    (2, 7, 128, 20, 30, 2, 8),
+    (2, 17, 32, 33, 66, 2, 6),
+    (2, 32, 64, 30, 44, 2, 7),
+    (2, 16, 32, 40, 40, 2, 6),
+    (2, 3, 16, 25, 31, 2, 6),
+    (2, 24, 64, 21, 37, 2, 7),
+    (4, 24, 128, 130, 250, 2, 8),
+    (8, 17, 32, 140, 200, 2, 6),
+    (2, 32, 32, 37, 45, 1, 6),
+    (2, 16, 16, 20, 33, 1, 6),
+    (2, 24, 128, 19, 23, 1, 8),
+    (2, 32, 64, 17, 40, 1, 7),
+    (6, 32, 32, 70, 100, 1, 6),
 ]
 
 
-@pytest.mark.parametrize("n,cin,cout,h,w,n_tile", S2_CASES)
-def test_conv_stride2_resident_equals_generic(n, cin, cout, h, w, n_tile):
-    """The persistent stride-2 kernel walks K in the generic kernel's chunk
-    order, so its bf16 output equals the default tiling's bit for bit; the
-    default tiling's float output (oracle-checked above) rounds to it."""
+@pytest.mark.parametrize("n,cin,cout,h,w,stride,n_tile", S2_CASES)
+def test_conv_few_channel_resident_equals_generic(n, cin, cout, h, w, stride, n_tile):
+    """The persistent few-channel kernel walks K in the generic kernel's
+    chunk order, so its bf16 output equals the default tiling's bit for bit;
+    the default tiling's float output (oracle-checked above) rounds to it."""
     from paper_2112_10603_amd import op_conv
-    print(f"case stride-2 resident n={n} cin={cin} cout={cout} h={h} w={w} tile={n_tile}", flush=True)
+    print(f"case few-channel resident n={n} cin={cin} cout={cout} h={h} w={w} s={stride} tile={n_tile}",
+          flush=True)
     rng = np.random.default_rng(n * 13 + cin * 7 + cout + h)
     x = rng.standard_normal((n, cin, h, w)).astype(np.float32)
     wt = (rng.standard_normal((cout, cin, 3, 3)) / np.sqrt(9 * cin)).astype(np.float32)
     b = rng.standard_normal(cout).astype(np.float32)
     xd = torch.from_numpy(x).cuda()
-    base = op_conv(xd, wt, b, stride=2, relu=True, precision="bf16", act_out=True).cpu()
-    got = op_conv(xd, wt, b, stride=2, relu=True, precision="bf16", n_tile=n_tile, tile_w=16,
+    base = op_conv(xd, wt, b, stride=stride, relu=True, precision="bf16", n_tile=128 if cout > 64 else 32,
+                   tile_w=16, act_out=True).cpu()
+    got = op_conv(xd, wt, b, stride=stride, relu=True, precision="bf16", n_tile=n_tile, tile_w=16,
                   act_out=True).cpu()
     assert torch.equal(got, base), (got - base).abs().max().item()
     if n == 2:
         xr = torch.from_numpy(x).bfloat16().double().numpy()
         wr = torch.from_numpy(wt).bfloat16().double().numpy()
-        ref = _ref(xr, wr, b.astype(np.float64), 2, False, True)
-        absref = _ref(np.abs(xr), np.abs(wr), np.abs(b).astype(np.float64), 2, False, False)
+        ref = _ref(xr, wr, b.astype(np.float64), stride, False, True)
+        absref = _ref(np.abs(xr), np.abs(wr), np.abs(b).astype(np.float64), stride, False, False)
         # bf16 output: half an ulp of the value on top of the accumulation bound
         assert np.all(np.abs(got.numpy() - ref) <= 2e-5 * absref + np.abs(ref) * 2.0 ** -8 + 1e-6)
 
 
 def test_conv_stride2_resident_rejects():
-    """Float outputs, 64 input channels, or a stride-1 conv are refused."""
+    """Float outputs or 64 input channels are refused."""
     from paper_2112_10603_amd import op_conv
     from paper_2112_10603_amd.ffv import FfvError
     print("case stride-2 resident rejects", flush=True)
@@ -411,8 +418,6 @@ def test_conv_stride2_resident_rejects():
     b = np.zeros(128, np.float32)
     with pytest.raises(FfvError):
         op_conv(x, wt, b, stride=2, precision="bf16", n_tile=8, tile_w=16)  # float output
-    with pytest.raises(FfvError):
-        op_conv(x, wt, b, stride=1, precision="bf16", n_tile=8, tile_w=16, act_out=True)
     x2 = torch.from_numpy(rng.standard_normal((1, 64, 20, 20)).astype(np.float32)).cuda()
     w2 = rng.standard_normal((128, 64, 3, 3)).astype(np.float32)
     with pytest.raises(FfvError):
