@@ -2,7 +2,9 @@
 // layers with few output channels over a stride-1 3x3 neighbourhood whose
 // whole weight matrix fits next to two input halos (supplementary layer
 // table: the flow/mask heads of the VIBlocks, phase-merged 4x4 transposed
-// convs, and the stride-1 3x3 convs of the narrow U-Net levels).
+// convs, and the stride-1 3x3 convs of the narrow U-Net levels), and for
+// one output phase of a 4x4 stride-2 transposed conv (four 2x2 taps over
+// the same neighbourhood; a workgroup keeps one phase's weights).
 //
 // These layers have one or two channel slices per output block, so a
 // kernel that loads each block's input and weights and then computes has
@@ -42,10 +44,10 @@ struct Resident {
 // (the weights of every output channel must fit the resident buffer).
 inline bool resident_ok(const ConvArgs& a, int bn, int elem_bytes) {
   const int bk = Resident::KB / elem_bytes;
-  const bool s1 = (a.transposed == 0 && a.stride == 1) || a.transposed == 2;
+  const bool nb = (a.transposed == 0 && a.stride == 1 && a.taps == 9) || (a.transposed == 2 && a.taps == 9) ||
+                  (a.transposed == 1 && a.taps == 4);
   const long row_bytes = (long)a.K_pad * elem_bytes;
-  if (!s1 || a.taps != 9 || a.cin_pad % bk != 0 || a.K_pad != 9 * a.cin_pad || row_bytes % 16 != 0)
-    return false;
+  if (!nb || a.cin_pad % bk != 0 || a.K_pad != a.taps * a.cin_pad || row_bytes % 16 != 0) return false;
   const long rc = row_bytes / 16;
   return a.Hi == a.Ho && a.Wi == a.Wo && a.n_rows <= bn && bn <= a.cout_pad &&
          bn * (rc + 1) <= Resident::W_VECS && a.tile_w == Resident::TW;
@@ -59,7 +61,8 @@ inline bool resident_ok(const ConvArgs& a, int bn, int elem_bytes) {
 // 16-byte channel runs (16-byte stores), EPI 2 for float outputs of a
 // 32-column tile (one lane per output pixel, float4 accesses, in-place
 // accumulation). EPI 0: lanes store single values from registers.
-template <typename T, int BN, int EPI>
+// TAPS 4: one output phase of a transposed conv per workgroup.
+template <typename T, int BN, int EPI, int TAPS>
 __global__ __launch_bounds__(Resident::NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void conv_resident(ConvArgs a, int n_tiles) {
   constexpr bool SW = EPI != 0;
@@ -80,10 +83,23 @@ void conv_resident(ConvArgs a, int n_tiles) {
   const int rc = a.K_pad * (int)sizeof(T) / 16, rcp = rc + 1;
   const int n_slices = a.cin_pad / BK;
 
+  // Per-phase launches: workgroup b serves phase (b / 8) % 4 (so every XCD
+  // has all four), with the remaining bits numbering it within its phase.
+  int G = gridDim.x, b = blockIdx.x, phase = 0;
+  if constexpr (TAPS == 4) {
+    if (G % 32 == 0) {
+      phase = (b >> 3) & 3;
+      b = (b & 7) | ((b >> 5) << 3);
+    } else {
+      phase = b & 3;
+      b >>= 2;
+    }
+    G >>= 2;
+  }
+  const int pyph = phase >> 1, pxph = phase & 1;
   // This workgroup's blocks: each XCD (workgroups round-robin over 8) owns a
   // contiguous range of blocks, so neighbouring blocks' shared halo rows
   // meet in its L2; its workgroups take the range's blocks in turn.
-  const int G = gridDim.x, b = blockIdx.x;
   int t_first = b, t_step = G, t_end = n_tiles;
   if (G % 8 == 0) {
     const int x = b & 7, q = n_tiles >> 3, r = n_tiles & 7;
@@ -96,7 +112,7 @@ void conv_resident(ConvArgs a, int n_tiles) {
   const int per_img = tiles_x * tiles_y;
 
   const T* in = reinterpret_cast<const T*>(a.in);
-  const T* wgt = reinterpret_cast<const T*>(a.wgt);
+  const T* wgt = reinterpret_cast<const T*>(a.wgt) + (long)phase * a.cout_pad * a.K_pad;
   const T* zero = reinterpret_cast<const T*>(a.zero);
 
   // resident weights: slot v = (row v / rcp, chunk v % rcp); the pitch's
@@ -145,8 +161,11 @@ void conv_resident(ConvArgs a, int n_tiles) {
   // previous tap consume the other, so LDS latency is not paid per MFMA.
   constexpr int QN = CH / 2;
   auto load_tap = [&](int buf, int s, int tap, uint4 (&fa)[QN], uint4 (&fb)[FN][QN]) {
-    const int hidx = (py + tap / 3) * HW + pxx + tap % 3;  // (y + dy + 1, x + dx + 1)
-    const int kc = (s * 9 + tap) * CH + lhalf * QN;        // (slice, tap) chunk in a weight row
+    // (y + dy + 1, x + dx + 1): the 3x3 neighbourhood, or the 2x2 taps of
+    // the phase, dy = py - tap / 2, dx = px - tap % 2
+    const int hidx = TAPS == 9 ? (py + tap / 3) * HW + pxx + tap % 3
+                               : (py + pyph - (tap >> 1) + 1) * HW + pxx + pxph - (tap & 1) + 1;
+    const int kc = (s * TAPS + tap) * CH + lhalf * QN;  // (slice, tap) chunk in a weight row
 #pragma unroll
     for (int q = 0; q < QN; ++q) fa[q] = Ah[buf][Halo::swz(hidx, lhalf * QN + q)];
 #pragma unroll
@@ -181,8 +200,8 @@ void conv_resident(ConvArgs a, int n_tiles) {
     uint4 fa[2][QN], fb[2][FN][QN];
     load_tap(buf, s, 0, fa[0], fb[0]);
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-      if (tap + 1 < 9) load_tap(buf, s, tap + 1, fa[(tap + 1) & 1], fb[(tap + 1) & 1]);
+    for (int tap = 0; tap < TAPS; ++tap) {
+      if (tap + 1 < TAPS) load_tap(buf, s, tap + 1, fa[(tap + 1) & 1], fb[(tap + 1) & 1]);
       // keep the next tap's reads ahead of this tap's MFMAs (the scheduler
       // would otherwise sink each read to its MFMA)
       __builtin_amdgcn_sched_barrier(0);
@@ -192,6 +211,10 @@ void conv_resident(ConvArgs a, int n_tiles) {
 
   // Epilogue of block t, whose last slice was computed from halo buffer buf.
   const int cout_m = merged ? a.cout : 1;
+  // output pixel of GEMM grid point (oy, ox) when not phase-merged
+  auto out_pix = [&](int oy, int ox) {
+    return TAPS == 4 ? (long)(2 * oy + pyph) * a.Wout + 2 * ox + pxph : (long)oy * a.Wout + ox;
+  };
   auto epilogue_staged = [&](int t, int buf) {
     // lane l holds, for fragment f, pixel wave*32 + l%32 and GEMM columns
     // f*32 + 8g + 4*(l/32) + q (g, q = 0..3). Bias, scale and ReLU in
@@ -260,7 +283,7 @@ void conv_resident(ConvArgs a, int n_tiles) {
       if (oy >= a.Ho || ox >= a.Wo || n >= a.n_rows) continue;
       long off;
       if (!merged) {
-        off = ((long)oy * a.Wout + ox) * a.out_ld + n;
+        off = out_pix(oy, ox) * a.out_ld + n;
       } else {
         const int ph = n / cout_m, o = n - ph * cout_m;
         off = ((long)(2 * oy + (ph >> 1)) * a.Wout + 2 * ox + (ph & 1)) * a.out_ld + o;
@@ -312,7 +335,7 @@ void conv_resident(ConvArgs a, int n_tiles) {
       const int row = wave * 32 + p;
       const int oy = ty0 + row / TW, ox = tx0 + row % TW;
       if (oy >= a.Ho || ox >= a.Wo) continue;
-      const long pix = merged ? (long)(2 * oy + (ph >> 1)) * a.Wout + 2 * ox + (ph & 1) : (long)oy * a.Wout + ox;
+      const long pix = merged ? (long)(2 * oy + (ph >> 1)) * a.Wout + 2 * ox + (ph & 1) : out_pix(oy, ox);
       float* dst = reinterpret_cast<float*>(a.out) + (long)img * a.out_img_stride + pix * a.out_ld;
       for (int c0 = 0; c0 < per; c0 += 4) {
         float v[4];
@@ -369,16 +392,14 @@ void conv_resident(ConvArgs a, int n_tiles) {
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int row = wave * 32 + (e >> 2) * 8 + lhalf * 4 + (e & 3);
-        int oy = ty0 + row / TW, ox = tx0 + row % TW;
+        const int oy = ty0 + row / TW, ox = tx0 + row % TW;
         if (oy >= a.Ho || ox >= a.Wo) continue;
-        if (merged) {  // the GEMM grid point's phase-(0, 0) output
-          oy *= 2;
-          ox *= 2;
-        }
+        // merged: the GEMM grid point's phase-(0, 0) output
+        const long pix = merged ? (long)(2 * oy) * a.Wout + 2 * ox : out_pix(oy, ox);
         float v = acc[f][e] * ws + bn;
         if (a.relu) v = fmaxf(v, 0.f);
         amax = fmaxf(amax, fabsf(v));
-        store_out<T>(a, (long)img * a.out_img_stride + ((long)oy * a.Wout + ox) * a.out_ld + col, o, v);
+        store_out<T>(a, (long)img * a.out_img_stride + pix * a.out_ld + col, o, v);
       }
       if (a.amax) atomicMax(reinterpret_cast<unsigned*>(a.amax) + o, __float_as_uint(amax));
     }
@@ -427,6 +448,25 @@ inline int device_cus() {
   return cus;
 }
 
+template <typename T, int BN, int TAPS>
+hipError_t launch_resident_epi(const ConvArgs& a, hipStream_t s, int grid, long tiles, bool staged16,
+                               bool staged32) {
+  if constexpr (sizeof(T) != 4) {
+    if (staged16) {
+      hipLaunchKernelGGL((conv_resident<T, BN, 1, TAPS>), dim3(grid), dim3(Resident::NT), 0, s, a, (int)tiles);
+      return hipGetLastError();
+    }
+  }
+  if constexpr (BN == 32) {
+    if (staged32) {
+      hipLaunchKernelGGL((conv_resident<T, BN, 2, TAPS>), dim3(grid), dim3(Resident::NT), 0, s, a, (int)tiles);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((conv_resident<T, BN, 0, TAPS>), dim3(grid), dim3(Resident::NT), 0, s, a, (int)tiles);
+  return hipGetLastError();
+}
+
 template <typename T, int BN>
 hipError_t launch_resident(const ConvArgs& a, hipStream_t s) {
   constexpr int VEC = 16 / (int)sizeof(T);
@@ -437,8 +477,12 @@ hipError_t launch_resident(const ConvArgs& a, hipStream_t s) {
                      ((a.Wo + Resident::TW - 1) / Resident::TW);
   if (tiles > 0x7fffffffL) return hipErrorInvalidValue;
   const int cus = device_cus();
-  const long per_xcd = cus >= 8 ? cus / 8 * 8 : cus;  // one workgroup per compute unit
-  const int grid = (int)(tiles < per_xcd ? tiles : per_xcd);
+  const long per_dev = cus >= 8 ? cus / 8 * 8 : cus;  // one workgroup per compute unit
+  // per-phase launches: a multiple of 4 workgroups, a quarter per phase
+  const long want = a.transposed == 1 ? 4 * tiles : tiles;
+  const int grid = a.transposed == 1 ? (int)(want < per_dev ? want : per_dev / 4 * 4)
+                                     : (int)(want < per_dev ? want : per_dev);
+  if (grid <= 0) return hipErrorInvalidValue;
   // staged epilogues: bf16/fp8 outputs in 16-byte channel runs, or float
   // outputs of a 32-column tile in 16-byte aligned pixels
   const int run = a.out_scale ? 16 : 8;
@@ -446,20 +490,8 @@ hipError_t launch_resident(const ConvArgs& a, hipStream_t s) {
   const bool staged16 = sizeof(T) != 4 && !a.out_f32 && a.cout % run == 0 && a.out_ld % run == 0 &&
                         a.out_img_stride % run == 0 && out16;
   const bool staged32 = BN == 32 && a.out_f32 && a.out_ld % 4 == 0 && a.out_img_stride % 4 == 0 && out16;
-  if constexpr (sizeof(T) != 4) {
-    if (staged16) {
-      hipLaunchKernelGGL((conv_resident<T, BN, 1>), dim3(grid), dim3(Resident::NT), 0, s, a, (int)tiles);
-      return hipGetLastError();
-    }
-  }
-  if constexpr (BN == 32) {
-    if (staged32) {
-      hipLaunchKernelGGL((conv_resident<T, BN, 2>), dim3(grid), dim3(Resident::NT), 0, s, a, (int)tiles);
-      return hipGetLastError();
-    }
-  }
-  hipLaunchKernelGGL((conv_resident<T, BN, 0>), dim3(grid), dim3(Resident::NT), 0, s, a, (int)tiles);
-  return hipGetLastError();
+  if (a.transposed == 1) return launch_resident_epi<T, BN, 4>(a, s, grid, tiles, staged16, staged32);
+  return launch_resident_epi<T, BN, 9>(a, s, grid, tiles, staged16, staged32);
 }
 
 }  // namespace convk

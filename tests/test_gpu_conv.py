@@ -72,18 +72,19 @@ def test_conv_kernel_vs_oracle(cin, cout, h, w, stride, transposed, precision):
 
 
 def _resident_fits(cin, cout, bn, transposed, stride, elem):
-    """Whether the resident-weight kernel runs the layer: a stride-1 or
-    phase-merged (transposed, at most 16 outputs) 3x3 neighbourhood, whole K
-    steps of channels, at most bn GEMM columns and weights that fit its LDS
-    buffer."""
-    merged = transposed and cout <= 16
-    if not ((not transposed and stride == 1) or merged):
+    """Whether the resident-weight kernel runs the layer: a stride-1 3x3
+    conv, a phase-merged transposed conv (at most 16 outputs) or one phase
+    of a transposed conv, whole K steps of channels, at most bn GEMM columns
+    and weights that fit its LDS buffer."""
+    if not transposed and stride != 1:
         return False
+    merged = transposed and cout <= 16
     rows = 4 * cout if merged else cout
+    taps = 4 if (transposed and not merged) else 9
     cin_pad = (cin + 7) // 8 * 8
     if cin_pad % (128 // elem) or rows > bn:
         return False
-    return bn * (9 * cin_pad * elem // 16 + 1) <= 4800
+    return bn * (taps * cin_pad * elem // 16 + 1) <= 4800
 
 
 VARIANT_CASES = [
@@ -259,6 +260,10 @@ RESIDENT_CASES = [
     (2, 64, 16, 17, 31, True),
     (8, 64, 16, 128, 160, False),
     (6, 128, 5, 100, 90, True),
+    (2, 128, 32, 13, 22, True),
+    (2, 64, 64, 15, 17, True),
+    (2, 64, 24, 19, 21, True),
+    (6, 128, 32, 70, 90, True),
 ]
 
 
@@ -331,6 +336,8 @@ STAGED_CASES = [
     (2, 64, 16, 17, 31, 0, True, 5, 16),
     (8, 64, 16, 128, 160, 1, False, 5, 16),
     (6, 64, 8, 60, 70, 0, True, 4, 16),
+    (2, 128, 32, 19, 23, 0, True, 4, 16),
+    (2, 64, 64, 21, 18, 0, True, 5, 16),
 ]
 
 
