@@ -379,6 +379,72 @@ __global__ void head_k(const T* u4, int ld, const float* wgt, const float* bias,
   o[2 * HW + p] = fminf(fmaxf(b.z + 2.f * r2 - 1.f, 0.f), 1.f);
 }
 
+// The same head for bf16 activations on the matrix cores: the 3x3 conv is a
+// GEMM with the 3 output channels (zero-padded to 32) as the A operand and
+// 32 pixels as B, K = (tap, channel) in 16-channel MFMA steps. A wave
+// computes groups of 32 consecutive pixels of the crop: lane l reads, per
+// tap, the 8 channels 8*(l/32).. of pixel l%32's neighbour (one 16-byte
+// load), and ends with that pixel's three pre-activations in its first
+// accumulators (lanes 0-31). The weights are rounded to bf16 (as every other
+// bf16 layer's) and laid out once per block as MFMA fragments in LDS; a
+// block covers HEAD_GROUPS groups per wave to amortise that.
+constexpr int HEAD_GROUPS = 16;
+
+template <int C>
+__global__ __launch_bounds__(TPB) void head_mfma_k(const bf16* u4, int ld, const float* wgt,
+                                                   const float* bias, const float* I2,
+                                                   const ViewDesc* views, int Hp, int Wp, int H, int W) {
+  constexpr int NC = C / 16;  // MFMAs per tap
+  constexpr int WAVES = TPB / 64;
+  __shared__ uint4 wtab[9 * NC * 64];  // [tap][j][lane] weight fragments
+  for (int i = threadIdx.x; i < 9 * NC * 64; i += TPB) {
+    const int ln = i & 63, tj = i >> 6, tap = tj / NC, j = tj - tap * NC;
+    const int n = ln & 31, h = ln >> 5;
+    bf16x8 w;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w[k] = (bf16)(n < 3 ? wgt[(n * C + 16 * j + 8 * h + k) * 9 + tap] : 0.f);
+    wtab[i] = __builtin_bit_cast(uint4, w);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lrow = lane & 31, lhalf = lane >> 5;
+  const int v = blockIdx.y;
+  const long HW = (long)H * W;
+  const bf16* base = u4 + (long)v * Hp * Wp * ld + 8 * lhalf;
+  const float bias0 = bias[0], bias1 = bias[1], bias2 = bias[2];
+  float* o = views[v].out;
+  for (int g = 0; g < HEAD_GROUPS; ++g) {
+    const long p = (((long)blockIdx.x * HEAD_GROUPS + g) * WAVES + wave) * 32 + lrow;
+    if (((long)blockIdx.x * HEAD_GROUPS + g) * WAVES * 32 >= HW) break;  // uniform over the block
+    const bool pin = p < HW;
+    const int y = pin ? (int)(p / W) : 0, x = pin ? (int)(p % W) : 0;
+    f32x16 acc;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+      const bool ok = pin && yy >= 0 && yy < Hp && xx >= 0 && xx < Wp;  // zero padding
+      const bf16* src = base + ((long)(ok ? yy : 0) * Wp + (ok ? xx : 0)) * ld;
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const uint4 av = ok ? *reinterpret_cast<const uint4*>(src + 16 * j) : make_uint4(0u, 0u, 0u, 0u);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+            __builtin_bit_cast(bf16x8, wtab[(tap * NC + j) * 64 + lane]), __builtin_bit_cast(bf16x8, av), acc, 0,
+            0, 0);
+      }
+    }
+    if (lhalf == 0 && pin) {
+      const float z0 = acc[0] + bias0, z1 = acc[1] + bias1, z2 = acc[2] + bias2;
+      const float4 b = ld4(I2 + ((long)v * Hp * Wp + (long)y * Wp + x) * 4);
+      const float r0 = 1.f / (1.f + expf(-z0)), r1 = 1.f / (1.f + expf(-z1)), r2 = 1.f / (1.f + expf(-z2));
+      o[p] = fminf(fmaxf(b.x + 2.f * r0 - 1.f, 0.f), 1.f);
+      o[HW + p] = fminf(fmaxf(b.y + 2.f * r1 - 1.f, 0.f), 1.f);
+      o[2 * HW + p] = fminf(fmaxf(b.z + 2.f * r2 - 1.f, 0.f), 1.f);
+    }
+  }
+}
+
 // -------------------------------------------------------- layout helpers
 template <typename T>
 __global__ void extract_k(const T* src, int ld, int C, long n_pix, float* dst) {
@@ -501,6 +567,17 @@ hipError_t launch_head(const void* u4, int ld, int C, const float* w, const floa
                        int W, DType dt, hipStream_t s) {
   if (n_img <= 0) return hipSuccess;
   if (C <= 0 || C > 64 || C % 8 != 0 || C > ld || ld % 8 != 0) return hipErrorInvalidValue;
+  if (dt == DType::BF16 && (C == 16 || C == 32)) {
+    const long per_block = (long)HEAD_GROUPS * (TPB / 64) * 32;  // groups of 32 pixels per wave
+    const dim3 g((unsigned)(((long)H * W + per_block - 1) / per_block), (unsigned)n_img);
+    if (C == 16)
+      hipLaunchKernelGGL(head_mfma_k<16>, g, dim3(TPB), 0, s, (const bf16*)u4, ld, w, b, I2, views, Hp, Wp,
+                         H, W);
+    else
+      hipLaunchKernelGGL(head_mfma_k<32>, g, dim3(TPB), 0, s, (const bf16*)u4, ld, w, b, I2, views, Hp, Wp,
+                         H, W);
+    return hipGetLastError();
+  }
   const dim3 grid = grid1((long)H * W, n_img);
   auto go = [&](auto tc) {
     constexpr int CC = decltype(tc)::value;
