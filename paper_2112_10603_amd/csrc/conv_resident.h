@@ -412,16 +412,24 @@ void conv_resident(ConvArgs a, int n_tiles) {
   // one pipeline of (block, slice) steps; step j computes from halo buffer
   // j & 1 while the next step's halo loads into the other one. The first
   // wait also covers the resident weights.
-  if (t_first < t_end && n_slices > 0) issue_halo(t_first, 0, 0);
+  // The issue cursor (it, is) runs one step ahead of the computed step; a
+  // single call site keeps the loop body small.
+  int it = t_first, is = 0;
+  auto advance = [&]() {
+    if (++is == n_slices) {
+      is = 0;
+      it += t_step;
+    }
+  };
+  if (it < t_end && n_slices > 0) issue_halo(it, is, 0);
+  advance();
   int j = 0;
   for (int t = t_first; t < t_end; t += t_step) {
     for (int s = 0; s < n_slices; ++s, ++j) {
       wait_vm<0>();
       __syncthreads();
-      if (s + 1 < n_slices)
-        issue_halo(t, s + 1, (j + 1) & 1);
-      else if (t + t_step < t_end)
-        issue_halo(t + t_step, 0, (j + 1) & 1);
+      if (it < t_end) issue_halo(it, is, (j + 1) & 1);
+      advance();
       compute(j & 1, s);
     }
     if constexpr (EPI == 1)
