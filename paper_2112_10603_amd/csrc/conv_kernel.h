@@ -260,6 +260,8 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   // offset (0, 0).
   constexpr int HA_IT = HALO ? (kHaloRows * CH + NT - 1) / NT : 1;
   const int hwid = a.tile_w + 2;
+  // hrow / hwid as (hrow * hw_mul) >> 16: exact for the halo rows (< 400)
+  const int hw_mul = (65536 + hwid - 1) / hwid;
   const int h_vecs = (BM / a.tile_w + 2) * hwid * CH;
   int h_off[HA_IT];
   int hb[FM];
@@ -448,7 +450,25 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
       };
       read_round(0, fa[0], fb[0]);
       if (kc + 1 < nk) issue_b(kc + 1, (kc + 1) & 1);
-      if (slice + 1 < n_slices) issue_halo(slice + 1, (slice + 1) & 1, tap);
+      if (slice + 1 < n_slices) {
+        // this tap's share of the next slice's halo: slots tid + i*NT,
+        // i = tap and tap + taps (per-phase convs have 4 taps, 6 pieces)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int i = tap + k * a.taps;
+          if (i * NT < h_vecs) {
+            const int v = tid + i * NT;
+            const int hrow = v / CH;
+            const int hy = (hrow * hw_mul) >> 16, hx = hrow - hy * hwid;
+            const int iy = ty0 - 1 + hy, ix = tx0 - 1 + hx;
+            const bool ok = v < h_vecs && iy >= 0 && iy < a.Hi && ix >= 0 && ix < a.Wi;
+            const T* src = ok ? in_img + ((iy * a.Wi + ix) * a.in_ld + C::logical_chunk(hrow, chunk) * VEC +
+                                          (slice + 1) * BK)
+                              : zero;
+            if (v < h_vecs) load_to_lds(src, &As[(slice + 1) & 1][i * NT + wave * 64]);
+          }
+        }
+      }
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         const int cur = r & 1;
