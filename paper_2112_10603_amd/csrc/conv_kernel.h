@@ -39,7 +39,12 @@
 // it, so the A bytes per slice drop from taps x BM rows to the halo's rows.
 // The next slice's halo is loaded in pieces, one share per tap step of the
 // current slice, into the second halo buffer; the weight tiles keep the
-// two-stage ring of the generic kernel.
+// two-stage ring of the generic kernel. A 256-column HALO tile over a
+// per-phase transposed conv with at most 128 outputs computes two output
+// phases at once, (py, 0) and (py, 1): they read the same halo (their taps
+// differ only in the column offset), each column group of waves takes one
+// phase, and the B tile stacks the two phases' weight rows, so a K step
+// does a full 256-column step's work without extra MFMAs.
 #pragma once
 
 #include "common.h"
@@ -194,7 +199,10 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WN, wn = wave % WN;
   const int merged = a.transposed == 2;
-  const int phase = a.transposed == 1 ? (int)blockIdx.z : 0;
+  // phase-paired: blockIdx.z is the phase row, the wave's column group the
+  // phase column (uniform per wave)
+  const bool paired = HALO && BN == 256 && WN == 2 && a.transposed == 1;
+  const int phase = a.transposed == 1 ? (paired ? 2 * (int)blockIdx.z + wn : (int)blockIdx.z) : 0;
   const int py = phase >> 1, px = phase & 1;
 
   // XCD-aware M-tile order: consecutive workgroup ids go round-robin over
@@ -211,10 +219,12 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   const int rem_t = mt - img_t * tiles_x * tiles_y;
   const int ty0 = (rem_t / tiles_x) * TH, tx0 = (rem_t % tiles_x) * TW;
   const int n0 = blockIdx.y * BN;
+  // output channel of this wave's first column (paired: within its phase)
+  const int col0 = paired ? 0 : n0 + wn * TN;
   const int chunk = tid % CH;  // this thread's chunk within a row
 
   const T* in = reinterpret_cast<const T*>(a.in);
-  const T* wgt = reinterpret_cast<const T*>(a.wgt) + (long)phase * a.cout_pad * a.K_pad;
+  const T* wgt = reinterpret_cast<const T*>(a.wgt);
   (void)VEC;
 
   // a step stays inside one tap when the channel count is a multiple of BK
@@ -285,7 +295,11 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   for (int i = 0; i < B_IT; ++i) {
     const int v = tid + i * NT;
     const int row = (B_VECS % NT == 0 || v < B_VECS) ? v / CH : 0;
-    b_ptr[i] = wgt + (long)(n0 + row) * a.K_pad + C::logical_chunk(row, chunk) * VEC;
+    // packed weights are [phase][cout_pad][K_pad]; paired tiles stack row r
+    // of phase (py, r / 128) at tile row r
+    const long prow = paired ? (long)(2 * (int)blockIdx.z + (row >> 7)) * a.cout_pad + (row & 127)
+                             : (long)(a.transposed == 1 ? (int)blockIdx.z : 0) * a.cout_pad + n0 + row;
+    b_ptr[i] = wgt + prow * a.K_pad + C::logical_chunk(row, chunk) * VEC;
   }
   const T* zero = reinterpret_cast<const T*>(a.zero);
   const int nk = a.K_pad / BK;
@@ -529,7 +543,7 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
       }
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        const int n = n0 + wn * TN + j * 32 + lrow;
+        const int n = col0 + j * 32 + lrow;
         long col;
         int o;
         if (!merged) {
@@ -576,7 +590,7 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
           const int c0 = j * 32 + 8 * g + 4 * lhalf;  // channel within the wave tile
-          const int n = n0 + wn * TN + c0;
+          const int n = col0 + c0;
           const bool nok = n < a.cout;  // cout is a multiple of 8: all four or none
           const int nb = nok ? n : 0;
           const float4 bias4 = *reinterpret_cast<const float4*>(a.bias + nb);
@@ -630,7 +644,7 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
         const int row = wm * TM + p;
         int oy = ty0 + row / TW;
         int ox = tx0 + row % TW;
-        const int n = n0 + wn * TN + ch * (16 / E);
+        const int n = col0 + ch * (16 / E);
         if (oy >= a.Ho || ox >= a.Wo || n >= a.cout) continue;
         if (a.transposed) {
           oy *= 2;
@@ -659,8 +673,11 @@ template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES, int SW
 hipError_t launch_variant(const ConvArgs& a, hipStream_t s) {
   using C = Conv<T, BM, BN, WM, WN, KB, STAGES, SWZ>;
   if (HALO && !halo_tile_ok(a, C::BK)) return hipErrorInvalidValue;
-  const int phases = a.transposed == 1 ? 4 : 1;
-  const int n_tiles = (a.n_rows + BN - 1) / BN;
+  // phase-paired 256-column HALO tiles: two phases per workgroup
+  const bool paired = HALO && BN == 256 && WN == 2 && a.transposed == 1;
+  if (paired && (a.n_rows > 128 || a.cout_pad < 128)) return hipErrorInvalidValue;
+  const int phases = a.transposed == 1 ? (paired ? 2 : 4) : 1;
+  const int n_tiles = paired ? 1 : (a.n_rows + BN - 1) / BN;
   // every B row a tile reads (n_tiles * BN of them) must exist in the packed weights
   if (a.K_pad % C::BK != 0 || a.cin_pad % C::VEC != 0 || a.n_rows <= 0 ||
       n_tiles * BN > a.cout_pad || a.in_ld % C::VEC != 0 || a.tile_w <= 0 || BM % a.tile_w != 0)

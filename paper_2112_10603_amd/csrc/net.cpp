@@ -1225,7 +1225,10 @@ Status Net::autotune(const float* const* left, const float* const* right, int n_
       const bool halo = tiles[ti] == ConvTile::H32 || resident || s2;
       const bool halo_big = tiles[ti] == ConvTile::H256 || tiles[ti] == ConvTile::H128;
       const int bn = conv_tile_bn(tiles[ti]);
-      if (bn >= 2 * rows32) continue;  // at least half of every tile's columns real
+      // at least half of every tile's columns real (a 256-column halo tile
+      // over a per-phase transposed conv holds two phases)
+      const bool paired = tiles[ti] == ConvTile::H256 && rec.a.transposed == 1 && rows32 <= 128;
+      if (bn >= 2 * rows32 && !paired) continue;
       if (tiles[ti] == ConvTile::H32 && !conv_halo_ok(rec.dt, rec.a)) continue;
       if (resident && !conv_resident_ok(rec.dt, rec.a, bn)) continue;
       if (s2 && !conv_resident_s2_ok(rec.dt, rec.a, bn)) continue;

@@ -198,6 +198,7 @@ HALO_TILE_CASES = [
     (128, 200, 9, 70, False),
     (256, 128, 13, 22, True),
     (128, 5, 23, 19, True),
+    (128, 40, 11, 19, True),
 ]
 
 
@@ -206,7 +207,8 @@ HALO_TILE_CASES = [
 def test_conv_halo_tiles_vs_oracle(cin, cout, h, w, transposed, precision):
     """The conv kernel's halo variant (one (TH+2) x (TW+2) input halo per
     channel slice, every tap read from LDS) against the oracle, for both N
-    tiles and the three block widths it accepts."""
+    tiles and the three block widths it accepts; on per-phase transposed
+    convs the 256-column tile computes two output phases at once."""
     from paper_2112_10603_amd import op_conv
     rng = np.random.default_rng(cin * 13 + cout + h)
     n = 2
@@ -338,6 +340,8 @@ STAGED_CASES = [
     (6, 64, 8, 60, 70, 0, True, 4, 16),
     (2, 128, 32, 19, 23, 0, True, 4, 16),
     (2, 64, 64, 21, 18, 0, True, 5, 16),
+    (2, 256, 128, 13, 22, 0, True, 3, 32),
+    (2, 128, 40, 11, 19, 0, True, 3, 8),
 ]
 
 
