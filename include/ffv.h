@@ -151,7 +151,8 @@ ffv_status ffv_autotune(ffv_net* net, const ffv_pair* views, int32_t n_pairs, co
  * Tuning table as text, one line per launch shape:
  * "layer fp8 Ho Wo n_img n_tile tile_w" ('#' starts a comment line); n_tile
  * is 256, 128, 64, 32, or h256, h128, h32 for the halo variants, r64, r32
- * for the resident-weight variants, s128, s64, s32 for the stride-2 ones.
+ * for the resident-weight variants, s128, s64, s32 for the few-channel ones,
+ * q256 for the 2 x 4-wave halo tile.
  * ffv_save_tuning writes the net's table; ffv_load_tuning merges a file's
  * entries into it (*n_loaded, nullable, = entries read) and rejects the
  * whole file on a malformed line, an unknown layer or a tile that does not
@@ -303,8 +304,10 @@ ffv_status ffv_stitch_cluster(const float* real_view, const float* const* left,
  * weights resident in LDS, 32 or 64 GEMM columns, for stride-1 and
  * phase-merged transposed convs with few output channels; 6, 7, 8 = the
  * persistent stride-2 kernel for 8 to 32 input channels with 32, 64 or 128
- * columns, weights resident, bf16 outputs in 16-byte channel runs only; a
- * variant that cannot run the layer gives FFV_ERR_DEVICE) and tile_w (0 =
+ * columns, weights resident, bf16 outputs in 16-byte channel runs only; 9 =
+ * the 256-column halo tile with 2 x 4 waves (all four phases of a
+ * transposed conv with at most 64 outputs in one workgroup); a variant that
+ * cannot run the layer gives FFV_ERR_DEVICE) and tile_w (0 =
  * default, else the
  * width of the 256-pixel block of a workgroup, a divisor of 256) pick the
  * kernel variant, as autotuning does; every choice gives the same result.

@@ -69,15 +69,19 @@ struct ConvArgs {
 // neighbourhoods and per-phase transposed convs; M-tile width 8, 16 or 32);
 // R32, R64: the persistent halo kernel with the layer's weights resident in
 // LDS (stride-1 3x3 neighbourhoods with at most 32/64 GEMM columns and small
-// weights; M-tile width 16); S32, S64, S128: the persistent stride-2 kernel
-// for 8 to 32 input channels, weights resident (M-tile width 16).
+// weights; M-tile width 16); S32, S64, S128: the persistent few-channel
+// kernel (stride 2 or 1, 8 to 32 input channels), weights resident (M-tile
+// width 16); Q256: the 256-column halo tile with its waves as 2 x 4 (on a
+// per-phase transposed conv with at most 64 outputs, all four phases in one
+// workgroup).
 enum class ConvTile : int {
-  N256 = 0, N128 = 1, N64 = 2, N32 = 3, H32 = 4, H256 = 5, H128 = 6, R32 = 7, R64 = 8, S32 = 9, S64 = 10, S128 = 11
+  N256 = 0, N128 = 1, N64 = 2, N32 = 3, H32 = 4, H256 = 5, H128 = 6, R32 = 7, R64 = 8, S32 = 9, S64 = 10, S128 = 11,
+  Q256 = 12
 };
 // N tile (output channels per workgroup) of a tile kind.
 inline int conv_tile_bn(ConvTile t) {
   switch (t) {
-    case ConvTile::N256: case ConvTile::H256: return 256;
+    case ConvTile::N256: case ConvTile::H256: case ConvTile::Q256: return 256;
     case ConvTile::N128: case ConvTile::H128: case ConvTile::S128: return 128;
     case ConvTile::N64: case ConvTile::R64: case ConvTile::S64: return 64;
     default: return 32;

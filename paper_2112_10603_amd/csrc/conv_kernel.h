@@ -40,11 +40,12 @@
 // The next slice's halo is loaded in pieces, one share per tap step of the
 // current slice, into the second halo buffer; the weight tiles keep the
 // two-stage ring of the generic kernel. A 256-column HALO tile over a
-// per-phase transposed conv with at most 128 outputs computes two output
-// phases at once, (py, 0) and (py, 1): they read the same halo (their taps
-// differ only in the column offset), each column group of waves takes one
-// phase, and the B tile stacks the two phases' weight rows, so a K step
-// does a full 256-column step's work without extra MFMAs.
+// per-phase transposed conv computes WN output phases at once (WN column
+// groups of waves): with 2, phases (py, 0) and (py, 1) for at most 128
+// outputs; with 4, all four for at most 64. The phases read the same halo
+// (their 2x2 taps differ only in offset), each column group takes one
+// phase, and the B tile stacks the phases' weight rows, so a K step does a
+// full 256-column step's work without extra MFMAs.
 #pragma once
 
 #include "common.h"
@@ -199,10 +200,11 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WN, wn = wave % WN;
   const int merged = a.transposed == 2;
-  // phase-paired: blockIdx.z is the phase row, the wave's column group the
-  // phase column (uniform per wave)
-  const bool paired = HALO && BN == 256 && WN == 2 && a.transposed == 1;
-  const int phase = a.transposed == 1 ? (paired ? 2 * (int)blockIdx.z + wn : (int)blockIdx.z) : 0;
+  // phase-grouped: the wave's column group is its phase (with two groups,
+  // blockIdx.z is the phase row); uniform per wave
+  const bool paired = HALO && BN == 256 && (WN == 2 || WN == 4) && a.transposed == 1;
+  const int phase =
+      a.transposed == 1 ? (paired ? (WN == 4 ? wn : 2 * (int)blockIdx.z + wn) : (int)blockIdx.z) : 0;
   const int py = phase >> 1, px = phase & 1;
 
   // XCD-aware M-tile order: consecutive workgroup ids go round-robin over
@@ -295,9 +297,9 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   for (int i = 0; i < B_IT; ++i) {
     const int v = tid + i * NT;
     const int row = (B_VECS % NT == 0 || v < B_VECS) ? v / CH : 0;
-    // packed weights are [phase][cout_pad][K_pad]; paired tiles stack row r
-    // of phase (py, r / 128) at tile row r
-    const long prow = paired ? (long)(2 * (int)blockIdx.z + (row >> 7)) * a.cout_pad + (row & 127)
+    // packed weights are [phase][cout_pad][K_pad]; phase-grouped tiles
+    // stack row r % TN of the r / TN-th phase of the group at tile row r
+    const long prow = paired ? (long)((WN == 4 ? 0 : 2 * (int)blockIdx.z) + row / TN) * a.cout_pad + row % TN
                              : (long)(a.transposed == 1 ? (int)blockIdx.z : 0) * a.cout_pad + n0 + row;
     b_ptr[i] = wgt + prow * a.K_pad + C::logical_chunk(row, chunk) * VEC;
   }
@@ -673,10 +675,10 @@ template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES, int SW
 hipError_t launch_variant(const ConvArgs& a, hipStream_t s) {
   using C = Conv<T, BM, BN, WM, WN, KB, STAGES, SWZ>;
   if (HALO && !halo_tile_ok(a, C::BK)) return hipErrorInvalidValue;
-  // phase-paired 256-column HALO tiles: two phases per workgroup
-  const bool paired = HALO && BN == 256 && WN == 2 && a.transposed == 1;
-  if (paired && (a.n_rows > 128 || a.cout_pad < 128)) return hipErrorInvalidValue;
-  const int phases = a.transposed == 1 ? (paired ? 2 : 4) : 1;
+  // phase-grouped 256-column HALO tiles: WN phases per workgroup
+  const bool paired = HALO && BN == 256 && (WN == 2 || WN == 4) && a.transposed == 1;
+  if (paired && (a.n_rows > BN / WN || a.cout_pad < BN / WN)) return hipErrorInvalidValue;
+  const int phases = a.transposed == 1 ? (paired ? 4 / WN : 4) : 1;
   const int n_tiles = paired ? 1 : (a.n_rows + BN - 1) / BN;
   // every B row a tile reads (n_tiles * BN of them) must exist in the packed weights
   if (a.K_pad % C::BK != 0 || a.cin_pad % C::VEC != 0 || a.n_rows <= 0 ||

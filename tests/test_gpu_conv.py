@@ -140,7 +140,11 @@ def test_conv_tile_variants_agree(cin, cout, h, w, stride, transposed):
                           precision="bf16", n_tile=code).cpu()
             assert torch.equal(got, base), ("resident", bn, (got - base).abs().max().item())
     if (transposed or stride == 1) and cin % 64 == 0:
-        for code in (2, 3):  # 128- and 256-channel halo tiles
+        per_phase = transposed and cout > 16
+        codes = (2, 3) + ((9,) if not per_phase or cout <= 64 else ())
+        if per_phase and cout > 128:
+            codes = (2,)
+        for code in codes:  # 128- and 256-channel halo tiles, 2 x 4-wave layout
             for tile_w in (8, 16, 32):
                 got = op_conv(xd, wt, b, stride=max(stride, 1), transposed=transposed, relu=True,
                               precision="bf16", n_tile=code, tile_w=tile_w).cpu()
@@ -199,6 +203,7 @@ HALO_TILE_CASES = [
     (256, 128, 13, 22, True),
     (128, 5, 23, 19, True),
     (128, 40, 11, 19, True),
+    (256, 64, 13, 17, True),
 ]
 
 
@@ -212,6 +217,8 @@ def test_conv_halo_tiles_vs_oracle(cin, cout, h, w, transposed, precision):
     from paper_2112_10603_amd import op_conv
     rng = np.random.default_rng(cin * 13 + cout + h)
     n = 2
+    per_phase = transposed and cout > 16
+    codes = (2, 3) + ((9,) if not per_phase or cout <= 64 else ())
     x = rng.standard_normal((n, cin, h, w)).astype(np.float32)
     if transposed:
         wt = (rng.standard_normal((cin, cout, 4, 4)) / np.sqrt(4 * cin)).astype(np.float32)
@@ -226,7 +233,7 @@ def test_conv_halo_tiles_vs_oracle(cin, cout, h, w, transposed, precision):
     ref = _ref(xr, wr, b.astype(np.float64), 1, transposed, True)
     absref = _ref(np.abs(xr), np.abs(wr), np.abs(b).astype(np.float64), 1, transposed, False)
     xd = torch.from_numpy(x).cuda()
-    for code in (2, 3):
+    for code in codes:
         for tile_w in (8, 16, 32):
             print(f"case halo tile {code} tw={tile_w} cin={cin} cout={cout} h={h} w={w} T={transposed} "
                   f"{precision}", flush=True)
@@ -342,6 +349,8 @@ STAGED_CASES = [
     (2, 64, 64, 21, 18, 0, True, 5, 16),
     (2, 256, 128, 13, 22, 0, True, 3, 32),
     (2, 128, 40, 11, 19, 0, True, 3, 8),
+    (2, 256, 64, 13, 17, 0, True, 9, 16),
+    (2, 64, 256, 21, 35, 1, False, 9, 32),
 ]
 
 
