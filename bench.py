@@ -36,15 +36,14 @@ PEAK_HBM_GBS = 8000.0
 
 
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "conv_igemm_dense1080p_bf16_hbm_counters.md")
-CONV_SOURCES = [os.path.join(ROOT, "paper_2112_10603_amd", "csrc", f)
-                for f in ("conv_kernel.h", "conv_halo.h", "conv_resident.h", "conv.hip")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2112_10603_amd", "csrc", f)
+                  for f in ("conv_kernel.h", "conv_halo.h", "conv_resident.h", "conv_resident_s2.h", "conv.hip",
+                            "pixel.hip")]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the 256->256 conv class from the committed
-    counter summary (two rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE,
-    scaled by a plain copy), or None when the conv kernel sources no longer
-    hash to the value the counters were taken with."""
+def _counters_text():
+    """The committed counter summary, or None when the kernel sources no
+    longer hash to the value its counters were taken with."""
     import hashlib
     import re
     try:
@@ -52,13 +51,41 @@ def measured_traffic():
     except OSError:
         return None
     h = re.search(r"kernel-source-sha256: ([0-9a-f]{64})", text)
-    t = re.search(r"conv256-traffic-bytes-per-launch: (\d+)", text)
-    if not h or not t:
+    if not h:
         return None
     cur = hashlib.sha256()
-    for f in CONV_SOURCES:
+    for f in KERNEL_SOURCES:
         cur.update(open(f, "rb").read())
-    return int(t.group(1)) if cur.hexdigest() == h.group(1) else None
+    return text if cur.hexdigest() == h.group(1) else None
+
+
+def measured_traffic():
+    """HBM bytes per launch of the 256->256 conv class from the committed
+    counter summary (two rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE,
+    scaled by a plain copy), or None when it is stale."""
+    import re
+    text = _counters_text()
+    t = re.search(r"conv256-traffic-bytes-per-launch: (\d+)", text) if text else None
+    return int(t.group(1)) if t else None
+
+
+def measured_pixel_hbm():
+    """HBM GB/s of the per-pixel passes (warps, blend, resampling) over one
+    step, from the same committed counters: their FETCH + WRITE bytes over
+    their summed kernel-trace durations; None when stale."""
+    text = _counters_text()
+    if not text:
+        return None
+    gb = ms = 0.0
+    for line in text.splitlines():
+        f = [c.strip() for c in line.split("|")]
+        if len(f) >= 9 and f[5] == "pixel":
+            try:
+                ms += float(f[4])
+                gb += float(f[6]) + float(f[7])
+            except ValueError:
+                continue
+    return round(gb / (ms * 1e-3), 1) if ms > 0 else None
 
 
 def conv256_ideal_bytes(n_views, Hp, Wp, width=256):
@@ -363,12 +390,13 @@ def main():
     print(f"[bench] bf16 {ms_per_step:.2f} ms/step, {value:.1f} views/s", file=sys.stderr, flush=True)
 
     dom = stats["conv256"]
+    # the committed counters were taken on this workload only
+    default_workload = (H, W, args.cams, args.phases) == (1080, 1920, 8, 16)
     roof = None
     if dom["launches"] > 0:
         avg_ms = dom["ms"] / dom["launches"]
         flops_per_launch = dom["work"] / dom["launches"]
         achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
-        default_workload = (H, W, args.cams, args.phases) == (1080, 1920, 8, 16)
         traffic = measured_traffic() if default_workload else None
         Hp, Wp = (H + 15) // 16 * 16, (W + 15) // 16 * 16
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
@@ -377,6 +405,18 @@ def main():
                 "algorithmic_bytes_per_launch": round(conv256_ideal_bytes(n_views, Hp, Wp)),
                 "kernel": "conv_igemm bf16, 3x3 256->256 (VIBlock conv3-8)",
                 "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": flops_per_launch}
+    # per-pixel passes: algorithmic bytes (each input read once, each output
+    # written once) over their measured time, against the 8 TB/s HBM peak
+    px = stats["pixel"]
+    pixel_passes = None
+    if px["ms"] > 0:
+        gbs = px["work"] / (px["ms"] * 1e-3) / 1e9
+        pixel_passes = {"ms_per_step": round(px["ms"] / args.steps, 3),
+                        "algorithmic_gb_per_step": round(px["work"] / args.steps / 1e9, 2),
+                        "achieved_gbs_algorithmic": round(gbs, 1), "frac_of_hbm_peak": round(gbs / 8000.0, 3),
+                        "hbm_gbs_measured": measured_pixel_hbm() if default_workload else None,
+                        "kernels": "ingest, pyramid, stage transitions (warps), final warp + blend, "
+                                   "flow pyramid, context warps"}
     conv_ms = sum(stats[k]["ms"] for k in ("conv256", "conv", "convT"))
     conv_flops = sum(stats[k]["work"] for k in ("conv256", "conv", "convT"))
     breakdown = {k: {"launches": v["launches"], "ms_per_step": round(v["ms"] / args.steps, 3)}
@@ -510,6 +550,7 @@ def main():
         "serving": serving,
         "fp8_4k": fp8,
         "inference_modes": modes,
+        "pixel_passes": pixel_passes,
         "cluster_stitch": stitch,
         "bf16_vs_fp32": None if fp32 is None else round(value / fp32["views_per_s"], 2),
         "conv_mfma_util": round(conv_flops / (conv_ms * 1e-3) / 1e12 / PEAK_BF16_TFLOPS, 4)
