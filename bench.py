@@ -36,18 +36,19 @@ PEAK_HBM_GBS = 8000.0
 
 
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "conv_igemm_dense1080p_bf16_hbm_counters.md")
+MFMA_FILE = os.path.join(ROOT, "profiles", "conv_igemm_dense1080p_bf16_mfma_util.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2112_10603_amd", "csrc", f)
                   for f in ("conv_kernel.h", "conv_halo.h", "conv_resident.h", "conv_resident_s2.h", "conv.hip",
                             "pixel.hip")]
 
 
-def _counters_text():
-    """The committed counter summary, or None when the kernel sources no
+def _counters_text(path=COUNTERS_FILE):
+    """A committed counter summary, or None when the kernel sources no
     longer hash to the value its counters were taken with."""
     import hashlib
     import re
     try:
-        text = open(COUNTERS_FILE).read()
+        text = open(path).read()
     except OSError:
         return None
     h = re.search(r"kernel-source-sha256: ([0-9a-f]{64})", text)
@@ -86,6 +87,26 @@ def measured_pixel_hbm():
             except ValueError:
                 continue
     return round(gb / (ms * 1e-3), 1) if ms > 0 else None
+
+
+def measured_mfma_busy():
+    """MFMA-busy fraction of the convolutions from the committed rocprofv3
+    --pmc summary (MfmaUtil: SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE
+    times the SIMD count, each launch weighted by its trace duration), or
+    None when it is stale."""
+    import re
+    text = _counters_text(MFMA_FILE)
+    if not text:
+        return None
+    out = {}
+    for key in ("conv256", "conv", "convT", "all-convs"):
+        m = re.search(rf"^mfma-busy-{key}: ([0-9.]+)$", text, re.M)
+        if m:
+            out[key.replace("-", "_")] = float(m.group(1))
+    if not out:
+        return None
+    out["counter"] = "MfmaUtil = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x SIMDs), duration-weighted"
+    return out
 
 
 def conv256_ideal_bytes(n_views, Hp, Wp, width=256):
@@ -555,6 +576,7 @@ def main():
         "bf16_vs_fp32": None if fp32 is None else round(value / fp32["views_per_s"], 2),
         "conv_mfma_util": round(conv_flops / (conv_ms * 1e-3) / 1e12 / PEAK_BF16_TFLOPS, 4)
         if conv_ms > 0 else None,
+        "mfma_busy_rocprof": measured_mfma_busy() if default_workload else None,
         "kernel_ms_per_step": breakdown,
         "autotune": tune,
         "timed_as": "one hipGraph replay per step (captured on the first warm-up call), "
