@@ -65,6 +65,24 @@ __device__ inline void load8(const T* src, float (&v)[8]) {
   }
 }
 
+// Workgroup order of a (pixel blocks x views) grid for the final warp and
+// blend. Consecutive workgroup ids go to the 8 XCDs in turn, each with its
+// own L2; every XCD instead takes a contiguous range of an order that
+// visits one pixel block of every view before the next block, so the views
+// of a camera pair running together on an XCD read the same camera rows
+// from its L2. (Measured: 11 % faster for the final pass at 1080p x 112
+// views; the stage transition, whose output streams are wider, and the
+// other passes measured equal or slower with it.)
+__device__ inline void view_fastest_order(long& bx, int& v) {
+  const unsigned long gx = gridDim.x, gy = gridDim.y;
+  const unsigned long total = gx * gy;
+  const unsigned long id = (unsigned long)blockIdx.y * gx + blockIdx.x;
+  const unsigned long q = total >> 3, r = total & 7, x = id & 7;
+  const unsigned long lg = x * q + (x < r ? x : r) + (id >> 3);
+  bx = (long)(lg / gy);
+  v = (int)(lg - (unsigned long)bx * gy);
+}
+
 // Half-pixel-centre source coordinate for resampling n_in -> n_out.
 __device__ inline void hp_tap(int i, int n_in, int n_out, int& i0, int& i1, float& w) {
   float s = ((float)i + 0.5f) * ((float)n_in / (float)n_out) - 0.5f;
@@ -209,9 +227,11 @@ __global__ void transition_k(const ViewDesc* views, const CamDev* cams, int leve
 template <typename T>
 __global__ void final_k(const ViewDesc* views, const CamDev* cams, const float* FM, int h, int w,
                         float* I2, T* x0u, int ld) {
-  const int v = blockIdx.y;
+  long bx;
+  int v;
+  view_fastest_order(bx, v);
   const long P = (long)h * w;
-  const long p = (long)blockIdx.x * TPB + threadIdx.x;
+  const long p = bx * TPB + threadIdx.x;
   if (p >= P) return;
   const ViewDesc d = views[v];
   const int y = (int)(p / w), xx = (int)(p % w);
