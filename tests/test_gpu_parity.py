@@ -173,6 +173,23 @@ def test_bf16_psnr_hd_crop(wfile, oracle_w):
     net.close()
 
 
+@pytest.mark.parametrize("H,W,t", [(72, 136, 0.3), (33, 17, 0.0)])
+def test_ragged_bf16_psnr(wfile, oracle_w, H, W, t):
+    """BF16 at sizes whose pixel count is not a multiple of the output
+    head's 32-pixel groups or of its blocks: every pass's ragged tail, the
+    head's partly filled last pair of groups included."""
+    print(f"case ragged bf16 {H}x{W} t={t}", flush=True)
+    xl, xr = scenes.random_pair(23, H, W, d_max=5.0)
+    net = _net(wfile, "bf16")
+    out = net.interpolate([(xl.to(DEV), xr.to(DEV))], [t])[0, 0].cpu().numpy()
+    ref = O.vinet_forward(xl.numpy(), xr.numpy(), t, oracle_w)
+    p = psnr(out, ref)
+    print(f"  PSNR {p:.2f} dB, max-abs {np.abs(out - ref).max():.3e}")
+    assert np.isfinite(out).all()
+    assert p >= 45.0
+    net.close()
+
+
 def test_argument_errors(wfile):
     from paper_2112_10603_amd import FfvError
     net = _net(wfile)
