@@ -181,6 +181,10 @@ ffv_status ffv_calibrate(ffv_net* net, const ffv_pair* pair, float t);
 /* Serving (enabled when ffv_opts.hbm_budget_bytes > 0)                     */
 /* ---------------------------------------------------------------------- */
 /*
+ * While serving is on, ffv_autotune, ffv_load_tuning, ffv_calibrate and
+ * ffv_set_profiling pause admission and wait for the batches in flight
+ * before they change the net, and resume it when done.
+ *
  * Many users each ask for their own viewpoint between neighbouring cameras
  * (the paper's multi-user setting, section 2; one network evaluation per
  * view, section 3.1). Cameras are registered once; the library keeps each
@@ -195,10 +199,12 @@ ffv_status ffv_calibrate(ffv_net* net, const ffv_pair* pair, float t);
  */
 
 /* Copy a DEVICE planar [3][H][W] float32 image in [0,1] as camera cam_id
- * and build its resident data (synchronous). Re-registering an id replaces
- * the camera after the batches in flight finish. Errors: FFV_ERR_ARG,
- * FFV_ERR_BUDGET (cameras alone exceed the budget), FFV_ERR_STATE (serving
- * off), FFV_ERR_OOM, FFV_ERR_DEVICE. */
+ * and build its resident data (synchronous). Re-registering an id with an
+ * image of the same size replaces the camera after the batches in flight
+ * finish (queued requests then read the new image); a different size is
+ * FFV_ERR_ARG. If rebuilding a replaced camera fails, the id is
+ * unregistered. Errors: FFV_ERR_ARG, FFV_ERR_BUDGET (cameras alone exceed
+ * the budget), FFV_ERR_STATE (serving off), FFV_ERR_OOM, FFV_ERR_DEVICE. */
 ffv_status ffv_register_camera(ffv_net* net, int32_t cam_id, const float* image, int32_t height,
                                int32_t width);
 
@@ -214,14 +220,20 @@ typedef struct {
   double t_submit, t_admit, t_launch, t_done; /* seconds, steady clock */
 } ffv_timing;
 
-/* Queue a request (non-blocking, thread-safe). Errors: FFV_ERR_ARG (unknown
- * camera, sizes differ, t outside [0,1], null out), FFV_ERR_BUDGET (one view
- * can never fit the budget), FFV_ERR_STATE (serving off). */
+/* Queue a request (non-blocking, thread-safe). `out` must hold [3][H][W]
+ * floats of the cameras' size (the library cannot check a raw pointer).
+ * Errors: FFV_ERR_ARG (unknown camera, sizes differ, t outside [0,1], null
+ * out), FFV_ERR_BUDGET (one view can never fit the budget), FFV_ERR_STATE
+ * (serving off, or an FP8 net not yet calibrated). */
 ffv_status ffv_submit(ffv_net* net, const ffv_request* req, uint64_t* ticket);
 
 /* FFV_PENDING while queued or running; FFV_OK once the output is written
- * (fills *timing if non-NULL; the ticket is then collected);
- * FFV_ERR_TICKET for unknown or collected tickets. Thread-safe. */
+ * (fills *timing if non-NULL; the ticket is then collected). If the
+ * request's batch failed, the batch's error: FFV_ERR_DEVICE (a launch could
+ * not be queued) or FFV_ERR_OOM (no workspace could be allocated while
+ * nothing else was running); the output is then undefined and the ticket
+ * is collected. FFV_ERR_TICKET for unknown or collected tickets.
+ * Thread-safe. */
 ffv_status ffv_poll(ffv_net* net, uint64_t ticket, ffv_timing* timing);
 
 /* Requests admitted and completed so far, requests queued now, and device
@@ -235,9 +247,17 @@ ffv_status ffv_serving_stats(ffv_net* net, int64_t* admitted, int64_t* completed
 
 /*
  * Copy an intermediate tensor of view 0 of the last ffv_interpolate call to
- * the DEVICE buffer dst as float32 [C][Hs][Ws] (C, Hs, Ws written to dims).
- * Names: "F0" "F1" "F2" (flow+mask, 5 channels, stage resolution),
- * "I2" (blended view, 3 channels, padded size).
+ * the DEVICE buffer dst as float32 [C][Hs][Ws] (C, Hs, Ws written to dims),
+ * at the padded size (multiples of 16) and its 2^-k levels. Names:
+ *   "F0" "F1" "F2"  flow + mask logit of Eq. 2 (5 channels) at stage s
+ *   "I2"            the Eq. 1 blend (3 channels)
+ *   "x0"            the refinement U-Net's input [X_l, X_r, W_l, W_r, M, F]
+ *   "d1".."d4"      U-Net encoder outputs (B, 2B, 4B, 8B channels at 2^-k)
+ *   "u1".."u4"      U-Net decoder outputs (4B, 2B, B, B/2 channels at 2^(k-4))
+ *   "cl1".."cl4", "cr1".."cr4"    context features of the left / right view
+ *   "wcl1".."wcl4", "wcr1".."wcr4" the same, warped to the virtual view
+ * (section 3.1, "Refinement Network"). The U-Net names describe the last
+ * chunk of views, which holds view 0 when debug taps are on.
  * Only available when the net was created with debug taps enabled
  * (ffv_set_debug). Errors: FFV_ERR_ARG (unknown name, capacity too small),
  * FFV_ERR_STATE (no taps recorded).
@@ -259,6 +279,16 @@ ffv_status ffv_set_debug(ffv_net* net, int32_t enable);
 ffv_status ffv_set_profiling(ffv_net* net, int32_t enable);
 ffv_status ffv_kernel_stats(ffv_net* net, const char* name, int64_t* launches, double* ms,
                             double* work);
+
+/*
+ * Fault injection for tests of the error paths: the N-th device allocation
+ * ("alloc:N") or the N-th serving batch launch ("launch:N") after this call
+ * fails with FFV_ERR_OOM / FFV_ERR_DEVICE before any device work is issued
+ * for it; entries may be joined with ','. NULL or "" disarms. The
+ * environment variable FFV_FAULT sets the same spec for a whole process
+ * (read once, unless this call came first).
+ */
+ffv_status ffv_debug_fault(const char* spec);
 
 /*
  * Multi-view cluster frame (the Multiview Organizer of section 3.2; the

@@ -6,6 +6,7 @@
 #include <string>
 
 #include "../../include/ffv.h"
+#include "fault.h"
 #include "net.h"
 
 struct ffv_net {
@@ -225,6 +226,7 @@ ffv_status ffv_register_camera(ffv_net* net, int32_t cam_id, const float* image,
 ffv_status ffv_submit(ffv_net* net, const ffv_request* req, uint64_t* ticket) {
   if (!net || !req || !ticket) return fail(FFV_ERR_ARG, "null argument");
   if (!net->net.server()) return fail(FFV_ERR_STATE, "serving is off (hbm_budget_bytes = 0)");
+  if (!net->net.ready()) return fail(FFV_ERR_STATE, "FP8 net needs ffv_calibrate first");
   ffv::Request r;
   r.cam_l = req->cam_left;
   r.cam_r = req->cam_right;
@@ -290,6 +292,12 @@ ffv_status ffv_set_debug(ffv_net* net, int32_t enable) {
 ffv_status ffv_set_profiling(ffv_net* net, int32_t enable) {
   if (!net) return fail(FFV_ERR_ARG, "null net");
   net->net.set_profiling(enable != 0);
+  return FFV_OK;
+}
+
+ffv_status ffv_debug_fault(const char* spec) {
+  ffv::fault_arm(spec);
+  g_last_error.clear();
   return FFV_OK;
 }
 

@@ -16,6 +16,8 @@
 #include <fstream>
 #include <sstream>
 
+#include "fault.h"
+#include "serve.h"
 #include "sha256.h"
 
 namespace ffv {
@@ -299,12 +301,11 @@ Geo Geo::of(int H, int W) {
   return g;
 }
 
-double now_seconds() {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
+Net::Net() = default;
 
 Net::~Net() {
-  server_.reset();
+  sched_.reset();
+  exec_.reset();
   if (device_ >= 0) hipSetDevice(device_);
   if (stream_) hipStreamSynchronize(stream_);
   drop_graphs();
@@ -322,6 +323,13 @@ Net::~Net() {
   }
   for (auto e : evt_pool_) hipEventDestroy(e);
   if (own_stream_ && stream_) hipStreamDestroy(stream_);
+}
+
+Status Net::dev_alloc(void** p, size_t bytes, const char* what) const {
+  *p = nullptr;
+  if (fault_hit("alloc"))
+    return Status::err(kErrOom, std::string("hipMalloc ") + what + ": injected fault (FFV_FAULT)");
+  return check(hipMalloc(p, bytes), what);
 }
 
 Status Net::check(hipError_t e, const char* what) const {
@@ -359,7 +367,7 @@ Status Net::init(const std::string& path, int precision, int device, hipStream_t
     FFV_TRY(check(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking), "hipStreamCreate"));
     own_stream_ = true;
   }
-  FFV_TRY(check(hipMalloc(&zero_, 256), "hipMalloc zero"));
+  FFV_TRY(dev_alloc(&zero_, 256, "zero"));
   FFV_TRY(check(hipMemset(zero_, 0, 256), "hipMemset zero"));
   layers_ = std::move(wf.layers);
   for (auto& kv : layers_) {
@@ -367,16 +375,16 @@ Status Net::init(const std::string& path, int precision, int device, hipStream_t
     plan_layer(L);
     if (L.name == "unet.head") {
       // evaluated by the head kernel in fp32, weights in file layout [3][C][3][3]
-      FFV_TRY(check(hipMalloc(&L.w_dev, L.w_host.size() * 4), "hipMalloc head"));
+      FFV_TRY(dev_alloc(&L.w_dev, L.w_host.size() * 4, "head weights"));
       FFV_TRY(check(hipMemcpy(L.w_dev, L.w_host.data(), L.w_host.size() * 4, hipMemcpyHostToDevice),
                     "copy head"));
     } else {
       std::vector<uint8_t> packed = pack_layer(L, dt_);
-      FFV_TRY(check(hipMalloc(&L.w_dev, packed.size()), "hipMalloc weights"));
+      FFV_TRY(dev_alloc(&L.w_dev, packed.size(), "weights"));
       FFV_TRY(check(hipMemcpy(L.w_dev, packed.data(), packed.size(), hipMemcpyHostToDevice),
                     "copy weights"));
     }
-    FFV_TRY(check(hipMalloc((void**)&L.b_dev, L.b_host.size() * 4), "hipMalloc bias"));
+    FFV_TRY(dev_alloc((void**)&L.b_dev, L.b_host.size() * 4, "bias"));
     FFV_TRY(check(hipMemcpy(L.b_dev, L.b_host.data(), L.b_host.size() * 4, hipMemcpyHostToDevice),
                   "copy bias"));
   }
@@ -489,12 +497,14 @@ Status Net::ensure_workspace(size_t bytes) {
     ws_ = nullptr;
     ws_bytes_ = 0;
   }
-  FFV_TRY(check(hipMalloc(&ws_, bytes), "hipMalloc workspace"));
+  FFV_TRY(dev_alloc(&ws_, bytes, "workspace"));
   ws_bytes_ = bytes;
   return Status::ok();
 }
 
 void Net::set_profiling(bool on) {
+  ServingPause pause(sched_.get());
+  std::lock_guard<std::mutex> lk(call_mu_);
   profiling_ = on;
   stats_.clear();
 }
@@ -551,6 +561,7 @@ void Net::prof_end(const Exec& x, const char* cls, double work) {
 }
 
 Status Net::kernel_stats(const std::string& name, long* launches, double* ms, double* work) {
+  std::lock_guard<std::mutex> lk(call_mu_);
   auto it = stats_.find(name);
   if (it == stats_.end()) {
     *launches = 0;
@@ -1038,6 +1049,8 @@ Status Net::run_call(const float* const* left, const float* const* right, int n_
   FFV_TRY(check(hipStreamSynchronize(stream_), "hipStreamSynchronize"));
   last_plan_ = vp;
   last_views_ws_ = xv.ws;
+  last_cam_l_ = blocks[li[0]];
+  last_cam_r_ = blocks[ri[0]];
   have_taps_ = true;
   if (profiling_) {
     if (ran)
@@ -1057,8 +1070,16 @@ Status Net::debug_tap(const std::string& name, float* dst, size_t cap, int dims[
   if (!have_taps_) return Status::err(-7, "no forward pass recorded");
   const ViewPlan& p = last_plan_;
   const Geo& g = p.g;
-  const char* src;
-  int C, ld, h, w;
+  const int B = base_width_;
+  const char* src = nullptr;
+  DType dt = dt_;
+  int C = 0, ld = 0, h = 0, w = 0;
+  // level k (1..4) of a tap name ending in a digit
+  const int k = name.empty() ? 0 : name.back() - '0';
+  const bool lvl_ok = k >= 1 && k <= 4;
+  const std::string stem = name.substr(0, name.size() - 1);
+  const int lv_ld[4] = {3 * B, 6 * B, 12 * B, 16 * B};
+  const int cw[4] = {B / 2, B, 2 * B, 4 * B};
   if (name == "F0" || name == "F1" || name == "F2") {
     const int s = name[1] - '0';
     h = g.Hp * (1 << s) / 4;
@@ -1066,12 +1087,58 @@ Status Net::debug_tap(const std::string& name, float* dst, size_t cap, int dims[
     src = last_views_ws_ + p.FM[s];
     C = 5;
     ld = 8;
+    dt = DType::F32;
   } else if (name == "I2") {
     h = g.Hp;
     w = g.Wp;
     src = last_views_ws_ + p.I2;
     C = 3;
     ld = 4;
+    dt = DType::F32;
+  } else if (name == "x0") {  // U-Net input [X_l, X_r, W_l, W_r, M, F]
+    h = g.Hp;
+    w = g.Wp;
+    src = last_views_ws_ + p.x0u;
+    C = 17;
+    ld = 24;
+  } else if (lvl_ok && (stem == "d" || stem == "u" || stem == "wcl" || stem == "wcr")) {
+    // U-Net level buffer k - 1 holds [u | d | wc_l | wc_r] at 2^-k of the
+    // padded size (the deepest: [d4 | wc_l | wc_r]); u4 has its own buffer
+    h = g.Hp >> k;
+    w = g.Wp >> k;
+    const int e = (int)dtype_size(dt_);
+    const int enc_w = B << (k - 1);  // d_k channels
+    const char* lvl = last_views_ws_ + p.lvl[k - 1];
+    ld = lv_ld[k - 1];
+    if (stem == "d") {
+      src = lvl + (size_t)(k < 4 ? enc_w : 0) * e;
+      C = enc_w;
+    } else if (stem == "u") {
+      C = (16 * B) >> (k + 1);  // 4B, 2B, B, B/2
+      if (k == 4) {
+        h = g.Hp;
+        w = g.Wp;
+        src = last_views_ws_ + p.u4;
+        ld = B / 2;
+      } else {
+        // u_k sits in the u slot of level buffer 3 - k, at twice its size
+        h = g.Hp >> (4 - k);
+        w = g.Wp >> (4 - k);
+        src = last_views_ws_ + p.lvl[3 - k];
+        ld = lv_ld[3 - k];
+      }
+    } else {
+      const int off = k < 4 ? 2 * enc_w : enc_w;
+      src = lvl + (size_t)(off + (stem == "wcr" ? cw[k - 1] : 0)) * e;
+      C = cw[k - 1];
+    }
+  } else if (lvl_ok && (stem == "cl" || stem == "cr")) {  // context features of either camera
+    const CamPlan c = cam_plan(g);
+    h = g.Hp >> k;
+    w = g.Wp >> k;
+    src = (stem == "cl" ? last_cam_l_ : last_cam_r_) + c.ctx[k - 1];
+    C = cw[k - 1];
+    ld = C;
   } else {
     return Status::err(-1, "unknown tap " + name);
   }
@@ -1080,7 +1147,7 @@ Status Net::debug_tap(const std::string& name, float* dst, size_t cap, int dims[
   dims[0] = C;
   dims[1] = h;
   dims[2] = w;
-  FFV_TRY(check(launch_extract(src, DType::F32, ld, C, (long)h * w, dst, stream_), "extract"));
+  FFV_TRY(check(launch_extract(src, dt, ld, C, (long)h * w, dst, stream_), "extract"));
   return check(hipStreamSynchronize(stream_), "sync");
 }
 
@@ -1095,6 +1162,8 @@ static std::vector<std::string> vib_chain(int s) {
 
 Status Net::calibrate(const float* left, const float* right, int H, int W, float t) {
   if (!fp8_) return Status::err(-7, "calibration applies to FP8 nets");
+  // served batches read the fp8 weights and scales this call rewrites
+  ServingPause pause(sched_.get());
   std::lock_guard<std::mutex> lk(call_mu_);
   FFV_TRY(check(hipSetDevice(device_), "hipSetDevice"));
   for (int s = 0; s < 3; ++s)
@@ -1187,6 +1256,8 @@ Status Net::quantize_vib_layers() {
 Status Net::autotune(const float* const* left, const float* const* right, int n_pairs, int H, int W,
                      const float* t, int n_t, float* out, int* n_tuned) {
   if (n_tuned) *n_tuned = 0;
+  // no served batch may run while launches are recorded and re-timed
+  ServingPause pause(sched_.get());
   // 1. run the call once, recording every conv launch (eager, so each
   //    launch passes through conv()); its output is the call's result
   std::lock_guard<std::mutex> lk(call_mu_);
@@ -1297,6 +1368,7 @@ Status Net::save_tuning(const std::string& path) {
 }
 
 Status Net::load_tuning(const std::string& path, int* n_loaded) {
+  ServingPause pause(sched_.get());
   std::lock_guard<std::mutex> lk(call_mu_);
   if (n_loaded) *n_loaded = 0;
   FILE* f = std::fopen(path.c_str(), "r");
@@ -1353,10 +1425,17 @@ Status Net::load_tuning(const std::string& path, int* n_loaded) {
 }
 
 Status Net::start_serving(size_t budget, float tick_ms, int max_batch_views) {
-  if (server_) return Status::err(-7, "serving already started");
-  server_.reset(new Server(this, budget, tick_ms, max_batch_views));
-  Status st = server_->start();
-  if (!st.good()) server_.reset();
+  if (sched_) return Status::err(kErrState, "serving already started");
+  exec_.reset(new HipExecutor(this));
+  Status st = exec_->init();
+  if (st.good()) {
+    sched_.reset(new Scheduler(exec_.get(), budget, tick_ms, max_batch_views));
+    st = sched_->start();
+  }
+  if (!st.good()) {
+    sched_.reset();
+    exec_.reset();
+  }
   return st;
 }
 

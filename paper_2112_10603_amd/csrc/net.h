@@ -11,25 +11,13 @@
 #include <memory>
 #include <mutex>
 #include <string>
-#include <thread>
 #include <vector>
 
 #include "common.h"
+#include "scheduler.h"
+#include "status.h"
 
 namespace ffv {
-
-struct Status {
-  int code = 0;  // ffv_status value
-  std::string msg;
-  static Status ok() { return Status(); }
-  static Status err(int c, const std::string& m) {
-    Status s;
-    s.code = c;
-    s.msg = m;
-    return s;
-  }
-  bool good() const { return code == 0; }
-};
 
 // One convolution layer as stored in the weights file, and packed on device.
 struct Layer {
@@ -108,11 +96,11 @@ struct ViewPlan {
   size_t total = 0;
 };
 
-class Server;
+class HipExecutor;
 
 class Net {
  public:
-  Net() = default;
+  Net();
   ~Net();
   Status init(const std::string& weights_path, int precision, int device, hipStream_t stream,
               size_t workspace_cap);
@@ -151,7 +139,9 @@ class Net {
 
   // serving
   Status start_serving(size_t budget, float tick_ms, int max_batch_views);
-  Server* server() { return server_.get(); }
+  Scheduler* server() { return sched_.get(); }
+  // Device allocation through the fault hook (FFV_FAULT=alloc:N).
+  Status dev_alloc(void** p, size_t bytes, const char* what) const;
 
   // building blocks (also used by the server)
   CamPlan cam_plan(const Geo& g) const;
@@ -194,7 +184,7 @@ class Net {
   bool t_plane_ = true;
   DType dt_ = DType::F32;
   bool fp8_ = false;          // FP8 VIBlocks (activation dtype elsewhere: bf16)
-  bool calibrated_ = false;
+  std::atomic<bool> calibrated_{false};  // read by submitting threads
   bool calibrating_ = false;
   int device_ = 0;
   hipStream_t stream_ = nullptr;
@@ -207,6 +197,8 @@ class Net {
   bool have_taps_ = false;
   ViewPlan last_plan_{};
   char* last_views_ws_ = nullptr;
+  char* last_cam_l_ = nullptr;  // camera blocks of view 0 of the last call
+  char* last_cam_r_ = nullptr;
   std::mutex call_mu_;        // serialises interpolate() per net
 
   // A timed kernel class interval: events recorded before and after.
@@ -264,92 +256,11 @@ class Net {
   hipEvent_t cur_start_ = nullptr;
   std::map<std::string, KernelStat> stats_;
 
-  std::unique_ptr<Server> server_;
+  // serving: the scheduler is destroyed before its executor
+  std::unique_ptr<HipExecutor> exec_;
+  std::unique_ptr<Scheduler> sched_;
 };
 
-// ----------------------------------------------------------------------
-// Serving: cameras registered once (resident image pyramid and context
-// features), requests (camera pair, t, output) submitted from any thread,
-// batched per tick under an HBM admission budget, each batch run on a slot
-// (stream + workspace) of its own so consecutive batches overlap on the
-// device.
 
-struct Request {
-  int cam_l = 0, cam_r = 0;
-  float t = 0.f;
-  float* out = nullptr;
-  uint64_t tag = 0;
-};
-
-struct Timing {
-  double t_submit = 0, t_admit = 0, t_launch = 0, t_done = 0;
-};
-
-class Server {
- public:
-  static constexpr int kMaxCams = 1024;
-  Server(Net* net, size_t budget, float tick_ms, int max_batch_views);
-  ~Server();
-  Status start();
-  Status register_camera(int cam_id, const float* image, int H, int W);
-  Status submit(const Request& r, uint64_t* ticket);
-  // done = true with the timing when finished (the ticket is then
-  // collected); done = false while queued or running.
-  Status poll(uint64_t ticket, Timing* timing, bool* done);
-  Status stats(long* admitted, long* completed, long* queued, size_t* bytes_in_use);
-
- private:
-  struct Camera {
-    Geo g;
-    char* block = nullptr;
-    int slot = -1;  // index into the device camera table
-  };
-  struct Ticket {
-    Request req;
-    Geo g;
-    Timing tm;
-    // 0 queued, 1 admitted, 2 done; set to 2 by the completion callback
-    // (release) after tm.t_done, without the scheduler lock
-    std::atomic<int> state{0};
-  };
-  struct Slot {
-    hipStream_t s = nullptr;
-    char* ws = nullptr;
-    size_t bytes = 0;
-    std::atomic<bool> busy{false};
-    std::vector<Ticket*> tickets;  // written before launch, read by the callback
-  };
-  struct Done {
-    Server* srv;
-    Slot* slot;  // stable: slots are never moved or freed while serving
-  };
-  static void on_done(void* p);
-  void loop();
-  void admit_and_launch();  // called with mu_ held
-  size_t view_bytes(const Geo& g, int n) const;
-
-  Net* net_;
-  size_t budget_;
-  float tick_ms_;
-  int max_batch_;
-  std::thread thr_;
-  std::mutex mu_;
-  std::condition_variable cv_;
-  bool stop_ = false;
-  std::map<int, Camera> cams_;
-  std::vector<int> free_cam_slots_;
-  CamDev* cam_table_ = nullptr;  // device table, kMaxCams entries
-  size_t resident_bytes_ = 0;
-  size_t slot_bytes_ = 0;
-  std::deque<uint64_t> queue_;
-  std::map<uint64_t, Ticket> tickets_;  // nodes are stable: callbacks hold Ticket*
-  uint64_t next_ticket_ = 1;
-  std::vector<std::unique_ptr<Slot>> slots_;
-  std::vector<std::unique_ptr<Done>> done_ctx_;
-  long n_admitted_ = 0;
-  std::atomic<long> n_completed_{0};
-};
-
-double now_seconds();
 
 }  // namespace ffv

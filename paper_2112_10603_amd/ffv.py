@@ -29,7 +29,7 @@ EXPORTS = ["ffv_default_opts", "ffv_create_net", "ffv_destroy_net", "ffv_interpo
            "ffv_last_error", "ffv_calibrate", "ffv_register_camera", "ffv_submit", "ffv_poll", "ffv_serving_stats",
            "ffv_debug_tap", "ffv_set_debug", "ffv_set_profiling", "ffv_kernel_stats", "ffv_op_conv",
            "ffv_autotune", "ffv_save_tuning", "ffv_load_tuning", "ffv_interpolate_blend",
-           "ffv_interpolate_recursive", "ffv_stitch_cluster"]
+           "ffv_interpolate_recursive", "ffv_stitch_cluster", "ffv_debug_fault"]
 
 
 class FfvError(RuntimeError):
@@ -123,6 +123,8 @@ def lib() -> ctypes.CDLL:
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                     ctypes.POINTER(ctypes.c_uint64)]
     L.ffv_serving_stats.restype = c_int
+    L.ffv_debug_fault.argtypes = [ctypes.c_char_p]
+    L.ffv_debug_fault.restype = c_int
     _lib = L
     return L
 
@@ -167,6 +169,7 @@ class Net:
         _check(L.ffv_create_net(os.fsencode(weights_path), ctypes.byref(opts), ctypes.byref(h)))
         self._h = h
         self.precision = precision
+        self._cam_shapes = {}  # registered camera id -> (H, W)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -257,12 +260,17 @@ class Net:
         torch.cuda.current_stream(self.device).synchronize()
         _check(lib().ffv_register_camera(self._h, cam_id, image.data_ptr(), int(image.shape[1]),
                                          int(image.shape[2])))
+        self._cam_shapes[cam_id] = (int(image.shape[1]), int(image.shape[2]))
 
     def submit(self, cam_left: int, cam_right: int, t: float, out: torch.Tensor,
                tag: int = 0) -> int:
         """Queue one view; ``out`` ([3, H, W] float32 CUDA) must stay alive
         until ``poll`` reports it done. Returns the ticket."""
         _dev_f32(out, "out")
+        hw = self._cam_shapes.get(cam_left)
+        if hw is not None and tuple(out.shape) != (3,) + hw:
+            raise ValueError(f"out must be [3, {hw[0]}, {hw[1]}] for camera {cam_left}, got "
+                             f"{list(out.shape)}")
         req = ffv_request(cam_left, cam_right, float(t), out.data_ptr(), tag)
         tk = ctypes.c_uint64()
         torch.cuda.current_stream(self.device).synchronize()
@@ -270,7 +278,9 @@ class Net:
         return tk.value
 
     def poll(self, ticket: int):
-        """None while pending; the timing dict once the view is written."""
+        """None while pending; the timing dict once the view is written.
+        Raises FfvError (e.g. FFV_ERR_DEVICE, FFV_ERR_OOM) when the view's
+        batch failed; the ticket is collected either way."""
         tm = ffv_timing()
         code = _check(lib().ffv_poll(self._h, ticket, ctypes.byref(tm)))
         if code == 1:
@@ -308,6 +318,12 @@ class Net:
         _check(lib().ffv_kernel_stats(self._h, name.encode(), ctypes.byref(n), ctypes.byref(ms),
                                       ctypes.byref(work)))
         return {"launches": n.value, "ms": ms.value, "work": work.value}
+
+
+def debug_fault(spec: str | None):
+    """Arm the library's fault-injection hook ("alloc:N", "launch:N"), or
+    disarm it with None (tests of the error paths)."""
+    _check(lib().ffv_debug_fault(spec.encode() if spec else None))
 
 
 def op_conv(x: torch.Tensor, weight, bias, stride: int = 1, transposed: bool = False,

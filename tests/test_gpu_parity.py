@@ -64,6 +64,37 @@ def test_small_fp32_parity_with_taps(wfile, oracle_w):
     net.close()
 
 
+@pytest.mark.parametrize("H,W", [(128, 128), (72, 136)])
+def test_refinement_stages_fp32(wfile, oracle_w, H, W):
+    """Stage by stage through the refinement path (section 3.1, "Refinement
+    Network"): the U-Net input, the context features of both views and their
+    warped copies at each level, every encoder and decoder output, against
+    the oracle's intermediates, relative to each tensor's magnitude."""
+    print(f"case refinement taps fp32 {H}x{W}", flush=True)
+    xl, xr = scenes.random_pair(23, H, W, d_max=6.0)
+    net = _net(wfile)
+    net.set_debug(True)
+    net.interpolate([(xl.to(DEV), xr.to(DEV))], [0.4])
+    taps = {}
+    O.vinet_forward(xl.numpy(), xr.numpy(), 0.4, oracle_w, taps)
+    want = {"x0": taps["x0"]}
+    for k in range(1, 5):
+        want[f"d{k}"] = taps[f"d{k}"]
+        want[f"u{k}"] = taps[f"u{k}"]
+        want[f"cl{k}"] = taps["ctx_l"][k - 1]
+        want[f"cr{k}"] = taps["ctx_r"][k - 1]
+        want[f"wcl{k}"] = taps["wc"][k - 1][0]
+        want[f"wcr{k}"] = taps["wc"][k - 1][1]
+    for name, ref in want.items():
+        got = net.debug_tap(name).cpu().numpy()
+        assert got.shape == ref.shape, (name, got.shape, ref.shape)
+        scale = max(1.0, float(np.abs(ref).max()))
+        e = float(np.abs(got - ref).max()) / scale
+        print(f"  {name:5s} {str(ref.shape):18s} rel max-abs {e:.2e}")
+        assert e <= 1e-4, (name, e)
+    net.close()
+
+
 @pytest.mark.parametrize("H,W,t", [(72, 136, 0.3), (48, 50, 1.0), (33, 17, 0.0)])
 def test_ragged_fp32_parity(wfile, oracle_w, H, W, t):
     """Sizes that are not multiples of 16 (replicate pad + crop), several

@@ -112,3 +112,89 @@ def test_serving_errors(wfile):
         tiny.submit(0, 1, 0.5, torch.empty_like(big))
     assert e.value.code == -3
     tiny.close()
+
+
+def test_serving_failed_batch_reports_error(wfile):
+    """A batch whose launch fails (host-side injected fault: nothing of it is
+    queued on the device) reports FFV_ERR_DEVICE on each of its tickets;
+    later batches run and match the view computed alone."""
+    from paper_2112_10603_amd import FfvError, Net, debug_fault
+    print("case serving launch fault", flush=True)
+    arc = scenes.camera_arc(43, 32, 48, 2, 32, (3.0, 8.0), 3.0, 0.01).to(DEV)
+    net = Net(wfile, "fp32", 0, hbm_budget_bytes=4 << 30, tick_ms=1.0)
+    net.register_camera(0, arc[0].contiguous())
+    net.register_camera(1, arc[1].contiguous())
+    outs = [torch.full((3, 32, 48), -7.0, device=DEV) for _ in range(4)]
+    debug_fault("launch:1")
+    try:
+        tks = [net.submit(0, 1, 0.25 * (k + 1), outs[k]) for k in range(4)]
+        codes = {}
+        t0 = time.time()
+        while len(codes) < len(tks) and time.time() - t0 < 60:
+            for k, tk in enumerate(tks):
+                if k in codes:
+                    continue
+                try:
+                    if net.poll(tk) is not None:
+                        codes[k] = 0
+                except FfvError as e:
+                    codes[k] = e.code
+            time.sleep(0.002)
+    finally:
+        debug_fault(None)
+    assert len(codes) == 4
+    assert codes[0] == -4, codes  # the first batch holds the first request
+    assert all(c in (0, -4) for c in codes.values())
+    torch.cuda.synchronize()
+    alone = Net(wfile, "fp32", 0)
+    for k in range(4):
+        if codes[k] == 0:
+            ref = alone.interpolate([(arc[0], arc[1])], [0.25 * (k + 1)])[0, 0]
+            assert torch.equal(outs[k], ref)
+        else:
+            assert torch.all(outs[k] == -7.0)  # never written
+    with pytest.raises(FfvError) as e:
+        net.poll(tks[0])  # collected with its error
+    assert e.value.code == -6
+    # later requests run normally
+    tk = net.submit(0, 1, 0.5, outs[0])
+    _wait(net, [tk])
+    assert torch.equal(outs[0], alone.interpolate([(arc[0], arc[1])], [0.5])[0, 0])
+    alone.close()
+    net.close()
+
+
+def test_serving_camera_size_and_out_shape(wfile):
+    from paper_2112_10603_amd import FfvError, Net
+    net = Net(wfile, "bf16", 0, hbm_budget_bytes=4 << 30)
+    a = torch.rand(3, 32, 32, device=DEV)
+    net.register_camera(0, a)
+    net.register_camera(1, a)
+    with pytest.raises(FfvError) as e:
+        net.register_camera(0, torch.rand(3, 48, 32, device=DEV))  # size change
+    assert e.value.code == -1
+    net.register_camera(0, torch.rand(3, 32, 32, device=DEV))  # same size: replaced
+    with pytest.raises(ValueError):
+        net.submit(0, 1, 0.5, torch.empty(3, 16, 16, device=DEV))
+    tk = net.submit(0, 1, 0.5, torch.empty(3, 32, 32, device=DEV))
+    _wait(net, [tk])
+    net.close()
+
+
+def test_alloc_fault_then_recover(wfile):
+    """An injected allocation failure of the workspace surfaces as
+    FFV_ERR_OOM; the next call allocates and runs."""
+    from paper_2112_10603_amd import FfvError, Net, debug_fault
+    net = Net(wfile, "fp32", 0)
+    xl, xr = scenes.small_pair()
+    pr = [(xl.to(DEV), xr.to(DEV))]
+    debug_fault("alloc:1")
+    try:
+        with pytest.raises(FfvError) as e:
+            net.interpolate(pr, [0.5])
+        assert e.value.code == -2
+    finally:
+        debug_fault(None)
+    out = net.interpolate(pr, [0.5])
+    assert torch.isfinite(out).all()
+    net.close()
