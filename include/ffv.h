@@ -348,6 +348,30 @@ ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, int32_t cin
                        int32_t stride, int32_t transposed, int32_t relu, int32_t n_tile,
                        int32_t tile_w, float* y, void* stream);
 
+/* Bytes of the per-device scratch array behind ffv_op_conv_noalloc. */
+#define FFV_OP_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/*
+ * ffv_op_conv without device allocation, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc). Arguments, layout, result and errors are those of
+ * ffv_op_conv, and it runs the same kernels, so the two give the same
+ * values bit for bit. Its device buffers (NHWC input copy, packed weights,
+ * bias, NHWC output, zero block, each rounded up to 256 bytes) live in one
+ * array of FFV_OP_NOALLOC_SCRATCH_BYTES per device, which the library holds
+ * from the first call on that device until the process ends. A layer whose
+ * buffers do not fit is rejected with FFV_ERR_ARG before any device work.
+ * The call works on the current device, orders its work on `stream`
+ * (NULL = default stream) and synchronises it before returning. Every call
+ * on a device shares that device's array, so calls that overlap in time on
+ * one device (other host threads, other streams) race; callers serialise
+ * them.
+ */
+ffv_status ffv_op_conv_noalloc(int32_t precision, const float* x, int32_t n, int32_t cin,
+                               int32_t h, int32_t w, const float* weight, const float* bias,
+                               int32_t cout, int32_t stride, int32_t transposed, int32_t relu,
+                               int32_t n_tile, int32_t tile_w, float* y, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,6 +8,7 @@
 #include "../../include/ffv.h"
 #include "fault.h"
 #include "net.h"
+#include "op_conv.h"
 
 struct ffv_net {
   ffv::Net net;
@@ -348,11 +349,14 @@ extern "C" ffv_status ffv_stitch_cluster(const float* real_view, const float* co
 
 // ---------------------------------------------------------------------------
 // Operator-level entry point (kernel unit tests).
-extern "C" ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, int32_t cin,
-                                  int32_t h, int32_t w, const float* weight, const float* bias,
-                                  int32_t cout, int32_t stride, int32_t transposed, int32_t relu,
-                                  int32_t n_tile, int32_t tile_w, float* y, void* stream) {
-  using namespace ffv;
+namespace ffv {
+
+ffv_status op_fail(int code, const char* msg) { return fail(code, msg); }
+
+ffv_status op_conv_run(const OpConvScratch* scratch, int32_t precision, const float* x, int32_t n,
+                       int32_t cin, int32_t h, int32_t w, const float* weight, const float* bias,
+                       int32_t cout, int32_t stride, int32_t transposed, int32_t relu, int32_t n_tile,
+                       int32_t tile_w, float* y, void* stream) {
   if (!x || !weight || !bias || !y) return fail(FFV_ERR_ARG, "null argument");
   const bool act_out = (precision & FFV_OP_ACT_OUT) != 0;
   precision &= ~FFV_OP_ACT_OUT;
@@ -379,24 +383,39 @@ extern "C" ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, 
   const int wo = L.transposed ? 2 * w : (w - 1) / stride + 1;
   std::vector<uint8_t> packed = pack_layer(L, dt);
   const size_t e = dtype_size(dt);
-  void *xin = nullptr, *wd = nullptr, *bd = nullptr, *yo = nullptr, *zr = nullptr;
-  auto cleanup = [&]() {
-    if (zr) hipFree(zr);
-    if (xin) hipFree(xin);
-    if (wd) hipFree(wd);
-    if (bd) hipFree(bd);
-    if (yo) hipFree(yo);
-  };
-  hipError_t err = hipMalloc(&xin, (size_t)n * h * w * L.cin_pad * e);
-  if (err == hipSuccess) err = hipMalloc(&wd, packed.size());
-  if (err == hipSuccess) err = hipMalloc(&bd, (size_t)cout * 4);
   // output as the network's layers write it (activation dtype), or float
   const DType out_dt = act_out ? dt : DType::F32;
-  if (err == hipSuccess) err = hipMalloc(&yo, (size_t)n * ho * wo * cout * dtype_size(out_dt));
-  if (err == hipSuccess) err = hipMalloc(&zr, 256);
-  if (err == hipSuccess) err = hipMemset(zr, 0, 256);
-  if (err == hipSuccess) err = hipMemcpy(wd, packed.data(), packed.size(), hipMemcpyHostToDevice);
-  if (err == hipSuccess) err = hipMemcpy(bd, bias, (size_t)cout * 4, hipMemcpyHostToDevice);
+  // the call's device buffers: NHWC input, packed weights, bias, NHWC output
+  // and a zero block for taps outside the image
+  const size_t sizes[5] = {(size_t)n * h * w * L.cin_pad * e, packed.size(), (size_t)cout * 4,
+                           (size_t)n * ho * wo * cout * dtype_size(out_dt), 256};
+  void* buf[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipError_t err = hipSuccess;
+  if (scratch) {
+    size_t need = 0;
+    for (size_t b : sizes) need += (b + 255) / 256 * 256;
+    if (need > scratch->cap)
+      return fail(FFV_ERR_ARG, "layer needs " + std::to_string(need) + " bytes of scratch; the no-allocation "
+                               "entry point holds " + std::to_string(scratch->cap));
+    char* p = static_cast<char*>(scratch->base);
+    for (int i = 0; i < 5; ++i) {
+      buf[i] = p;
+      p += (sizes[i] + 255) / 256 * 256;
+    }
+  } else {
+    for (int i = 0; i < 5 && err == hipSuccess; ++i) err = hipMalloc(&buf[i], sizes[i]);
+  }
+  void *xin = buf[0], *wd = buf[1], *bd = buf[2], *yo = buf[3], *zr = buf[4];
+  auto cleanup = [&]() {
+    if (scratch) return;
+    for (void* b : buf)
+      if (b) hipFree(b);
+  };
+  // (the copies are ordered on s and waited for before returning, so the
+  // host vectors they read outlive them)
+  if (err == hipSuccess) err = hipMemsetAsync(zr, 0, 256, s);
+  if (err == hipSuccess) err = hipMemcpyAsync(wd, packed.data(), packed.size(), hipMemcpyHostToDevice, s);
+  if (err == hipSuccess) err = hipMemcpyAsync(bd, bias, (size_t)cout * 4, hipMemcpyHostToDevice, s);
   if (err == hipSuccess) err = launch_pack_nhwc(x, n, cin, h, w, xin, L.cin_pad, dt, s);
   if (err == hipSuccess) {
     ConvArgs a{};
@@ -454,9 +473,21 @@ extern "C" ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, 
   for (int i = 0; err == hipSuccess && i < n; ++i)
     err = launch_extract((const char*)yo + (size_t)i * ho * wo * cout * dtype_size(out_dt), out_dt, cout, cout,
                          (long)ho * wo, y + (size_t)i * cout * ho * wo, s);
-  if (err == hipSuccess) err = hipStreamSynchronize(s);
+  // on an error the queued work still reads the buffers: wait before freeing
+  const hipError_t sync = hipStreamSynchronize(s);
+  if (err == hipSuccess) err = sync;
   cleanup();
   if (err != hipSuccess) return fail(FFV_ERR_DEVICE, hipGetErrorString(err));
   g_last_error.clear();
   return FFV_OK;
+}
+
+}  // namespace ffv
+
+extern "C" ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, int32_t cin,
+                                  int32_t h, int32_t w, const float* weight, const float* bias,
+                                  int32_t cout, int32_t stride, int32_t transposed, int32_t relu,
+                                  int32_t n_tile, int32_t tile_w, float* y, void* stream) {
+  return ffv::op_conv_run(nullptr, precision, x, n, cin, h, w, weight, bias, cout, stride, transposed, relu,
+                          n_tile, tile_w, y, stream);
 }

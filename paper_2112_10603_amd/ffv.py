@@ -29,7 +29,8 @@ EXPORTS = ["ffv_default_opts", "ffv_create_net", "ffv_destroy_net", "ffv_interpo
            "ffv_last_error", "ffv_calibrate", "ffv_register_camera", "ffv_submit", "ffv_poll", "ffv_serving_stats",
            "ffv_debug_tap", "ffv_set_debug", "ffv_set_profiling", "ffv_kernel_stats", "ffv_op_conv",
            "ffv_autotune", "ffv_save_tuning", "ffv_load_tuning", "ffv_interpolate_blend",
-           "ffv_interpolate_recursive", "ffv_stitch_cluster", "ffv_debug_fault"]
+           "ffv_interpolate_recursive", "ffv_stitch_cluster", "ffv_debug_fault", "ffv_op_conv_noalloc"]
+FFV_OP_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class FfvError(RuntimeError):
@@ -96,6 +97,8 @@ def lib() -> ctypes.CDLL:
     L.ffv_op_conv.argtypes = [c_int, c_void, c_int, c_int, c_int, c_int, c_void, c_void, c_int,
                               c_int, c_int, c_int, c_int, c_int, c_void, c_void]
     L.ffv_op_conv.restype = c_int
+    L.ffv_op_conv_noalloc.argtypes = L.ffv_op_conv.argtypes
+    L.ffv_op_conv_noalloc.restype = c_int
     L.ffv_autotune.argtypes = [c_void, ctypes.POINTER(ffv_pair), c_int, ctypes.POINTER(c_f), c_int,
                                c_void, ctypes.POINTER(c_int)]
     L.ffv_autotune.restype = c_int
@@ -328,12 +331,14 @@ def debug_fault(spec: str | None):
 
 def op_conv(x: torch.Tensor, weight, bias, stride: int = 1, transposed: bool = False,
             relu: bool = False, precision: str = "fp32", n_tile: int = 0,
-            tile_w: int = 0, act_out: bool = False) -> torch.Tensor:
+            tile_w: int = 0, act_out: bool = False, noalloc: bool = False) -> torch.Tensor:
     """One conv layer through the library's implicit-GEMM kernel.
     ``x``: [n, cin, h, w] float32 CUDA; ``weight``/``bias``: host arrays in
     the weights-file layout; ``n_tile``/``tile_w``: kernel variant (0 =
     default); ``act_out``: the layer writes activation-dtype output, as in
-    the network, returned widened to float32."""
+    the network, returned widened to float32; ``noalloc``: call
+    ffv_op_conv_noalloc (device buffers in the library's fixed scratch
+    array) instead of ffv_op_conv."""
     import numpy as np
     _dev_f32(x, "x")
     n, cin, h, w = x.shape
@@ -346,9 +351,10 @@ def op_conv(x: torch.Tensor, weight, bias, stride: int = 1, transposed: bool = F
         ho, wo = (h - 1) // stride + 1, (w - 1) // stride + 1
     y = torch.empty((n, cout, ho, wo), dtype=torch.float32, device=x.device)
     s = torch.cuda.current_stream(x.device)
-    _check(lib().ffv_op_conv(PRECISIONS[precision] | (FFV_OP_ACT_OUT if act_out else 0), x.data_ptr(), n, cin, h, w,
-                             wt.ctypes.data, bs.ctypes.data, cout, stride, 1 if transposed else 0,
-                             1 if relu else 0, n_tile, tile_w, y.data_ptr(), s.cuda_stream))
+    fn = lib().ffv_op_conv_noalloc if noalloc else lib().ffv_op_conv
+    _check(fn(PRECISIONS[precision] | (FFV_OP_ACT_OUT if act_out else 0), x.data_ptr(), n, cin, h, w,
+              wt.ctypes.data, bs.ctypes.data, cout, stride, 1 if transposed else 0,
+              1 if relu else 0, n_tile, tile_w, y.data_ptr(), s.cuda_stream))
     return y
 
 
