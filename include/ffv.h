@@ -152,7 +152,8 @@ ffv_status ffv_autotune(ffv_net* net, const ffv_pair* views, int32_t n_pairs, co
  * "layer fp8 Ho Wo n_img n_tile tile_w" ('#' starts a comment line); n_tile
  * is 256, 128, 64, 32, or h256, h128, h32 for the halo variants, r64, r32
  * for the resident-weight variants, s128, s64, s32 for the few-channel ones,
- * q256 for the 2 x 4-wave halo tile.
+ * q256 for the 2 x 4-wave halo tile, p256 for the halo tile whose two wave
+ * groups alternate MFMA and memory phases.
  * ffv_save_tuning writes the net's table; ffv_load_tuning merges a file's
  * entries into it (*n_loaded, nullable, = entries read) and rejects the
  * whole file on a malformed line, an unknown layer or a tile that does not
@@ -336,7 +337,9 @@ ffv_status ffv_stitch_cluster(const float* real_view, const float* const* left,
  * persistent stride-2 kernel for 8 to 32 input channels with 32, 64 or 128
  * columns, weights resident, bf16 outputs in 16-byte channel runs only; 9 =
  * the 256-column halo tile with 2 x 4 waves (all four phases of a
- * transposed conv with at most 64 outputs in one workgroup); a variant that
+ * transposed conv with at most 64 outputs in one workgroup); 10 = the
+ * 256-column halo tile (as 3) with its eight waves in two groups whose
+ * MFMA and memory phases alternate; a variant that
  * cannot run the layer gives FFV_ERR_DEVICE) and tile_w (0 =
  * default, else the
  * width of the 256-pixel block of a workgroup, a divisor of 256) pick the

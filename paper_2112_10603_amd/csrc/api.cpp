@@ -363,9 +363,9 @@ ffv_status op_conv_run(const OpConvScratch* scratch, int32_t precision, const fl
   if (precision != FFV_FP32 && precision != FFV_BF16) return fail(FFV_ERR_ARG, "precision");
   if (n <= 0 || cin <= 0 || h <= 0 || w <= 0 || cout <= 0) return fail(FFV_ERR_ARG, "sizes");
   if (!transposed && stride != 1 && stride != 2) return fail(FFV_ERR_ARG, "stride");
-  if (n_tile != 0 && (n_tile < 1 || n_tile > 9) && n_tile != 32 && n_tile != 64 && n_tile != 128 &&
+  if (n_tile != 0 && (n_tile < 1 || n_tile > 10) && n_tile != 32 && n_tile != 64 && n_tile != 128 &&
       n_tile != 256)
-    return fail(FFV_ERR_ARG, "n_tile must be 0, 1-9, 32, 64, 128 or 256");
+    return fail(FFV_ERR_ARG, "n_tile must be 0, 1-10, 32, 64, 128 or 256");
   if (tile_w < 0 || tile_w > 256 || (tile_w > 0 && 256 % tile_w != 0))
     return fail(FFV_ERR_ARG, "tile_w must be 0 or divide 256");
   const DType dt = precision == FFV_FP32 ? DType::F32 : DType::BF16;
@@ -464,6 +464,7 @@ ffv_status op_conv_run(const OpConvScratch* scratch, int32_t precision, const fl
       a.tile_w = 16;
     }
     if (n_tile == 9) tile = ConvTile::Q256;
+    if (n_tile == 10) tile = ConvTile::P256;
     if (n_tile >= 6 && n_tile <= 8) {
       tile = n_tile == 6 ? ConvTile::S32 : (n_tile == 7 ? ConvTile::S64 : ConvTile::S128);
       a.tile_w = 16;

@@ -73,15 +73,16 @@ struct ConvArgs {
 // kernel (stride 2 or 1, 8 to 32 input channels), weights resident (M-tile
 // width 16); Q256: the 256-column halo tile with its waves as 2 x 4 (on a
 // per-phase transposed conv with at most 64 outputs, all four phases in one
-// workgroup).
+// workgroup); P256: the H256 tile with its eight waves in two groups whose
+// MFMA and memory phases alternate (same results bit for bit).
 enum class ConvTile : int {
   N256 = 0, N128 = 1, N64 = 2, N32 = 3, H32 = 4, H256 = 5, H128 = 6, R32 = 7, R64 = 8, S32 = 9, S64 = 10, S128 = 11,
-  Q256 = 12
+  Q256 = 12, P256 = 13
 };
 // N tile (output channels per workgroup) of a tile kind.
 inline int conv_tile_bn(ConvTile t) {
   switch (t) {
-    case ConvTile::N256: case ConvTile::H256: case ConvTile::Q256: return 256;
+    case ConvTile::N256: case ConvTile::H256: case ConvTile::Q256: case ConvTile::P256: return 256;
     case ConvTile::N128: case ConvTile::H128: case ConvTile::S128: return 128;
     case ConvTile::N64: case ConvTile::R64: case ConvTile::S64: return 64;
     default: return 32;

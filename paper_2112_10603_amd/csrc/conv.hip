@@ -58,6 +58,8 @@ hipError_t launch_t(ConvTile tile, const ConvArgs& a, hipStream_t s) {
       return launch_variant<T, 256, 128, 4, 2, 128, 2, 1, true>(a, s);
     case ConvTile::Q256:
       return launch_variant<T, 256, 256, 2, 4, 128, 2, 1, true>(a, s);
+    case ConvTile::P256:
+      return launch_variant<T, 256, 256, 4, 2, 128, 2, 1, true, true>(a, s);
     case ConvTile::R32:
       return launch_resident<T, 32>(a, s);
     case ConvTile::R64:

@@ -94,6 +94,28 @@ __device__ inline void load_to_lds(const void* src, void* dst_wave_base) {
       : "memory");
 }
 
+// The same with a wave-uniform 64-bit base (scalar registers) and a 32-bit
+// per-lane byte offset: lane l reads sbase + voff and writes
+// dst_wave_base + 16*l. One offset register per lane serves every load
+// whose address differs only by a uniform amount.
+__device__ inline void load_to_lds_s(const void* sbase, uint32_t voff, void* dst_wave_base) {
+  const uint32_t lds = __builtin_amdgcn_readfirstlane((uint32_t)(size_t)(lptr_t)dst_wave_base);
+  // (readfirstlane returns a signed int: each half is widened as unsigned)
+  const uint64_t b = (uint64_t)(size_t)sbase;
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)b);
+  const uint64_t base = ((uint64_t)hi << 32) | (uint64_t)lo;
+  uint32_t saved;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\t"
+      "s_mov_b32 m0, %1\n\t"
+      "global_load_lds_dwordx4 %2, %3\n\t"
+      "s_mov_b32 m0, %0"
+      : "=&s"(saved)
+      : "s"(lds), "v"(voff), "s"(base)
+      : "memory");
+}
+
 // Wait until at most N vector-memory operations of this wave are
 // outstanding (gfx9 s_waitcnt encoding: vmcnt in bits 3:0 and 15:14; expcnt
 // and lgkmcnt left at their maxima).
@@ -171,10 +193,13 @@ struct Conv {
 constexpr int kHaloRows = 340;
 __host__ __device__ constexpr bool halo_width_ok(int tw) { return tw == 8 || tw == 16 || tw == 32; }
 
-template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES, int SWZ, bool SW, bool HALO>
+template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES, int SWZ, bool SW, bool HALO,
+          bool PP = false>
 __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   using C = Conv<T, BM, BN, WM, WN, KB, STAGES, SWZ>;
   static_assert(!HALO || (BM == 256 && STAGES == 2), "halo tiles: 256 pixels, two stages");
+  static_assert(!PP || (HALO && BN == 256 && WM * WN == 8 && C::CH == 8),
+                "two-group schedule: 256x256 halo tiles of eight waves, 128-byte steps");
   constexpr int NT = C::NT, CH = C::CH, BK = C::BK, VEC = C::VEC;
   // SW: the MFMAs take the weights as A (each lane then holds consecutive
   // channels of one pixel) and the output tile is staged through LDS for
@@ -189,7 +214,10 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   // an A buffer holds BM rows, or a slice's halo in the HALO variant
   constexpr int AROWS = HALO ? kHaloRows : BM;
   constexpr int RING_VECS = STAGES * (AROWS + BN) * CH;
-  constexpr int SMEM_VECS = (SW && BM * BN * 2 / 16 > RING_VECS) ? BM * BN * 2 / 16 : RING_VECS;
+  // epilogue: the staged output tile (SW), then 3 x BN per-channel floats
+  constexpr int PRM_OFF_VECS = SW ? BM * BN * 2 / 16 : 0;
+  constexpr int EPI_VECS = PRM_OFF_VECS + 3 * BN * 4 / 16;
+  constexpr int SMEM_VECS = EPI_VECS > RING_VECS ? EPI_VECS : RING_VECS;
   __shared__ __attribute__((aligned(16))) uint4 smem[SMEM_VECS];
   uint4 (*As)[AROWS * CH] = reinterpret_cast<uint4 (*)[AROWS * CH]>(smem);
   uint4 (*Bs)[BN * CH] = reinterpret_cast<uint4 (*)[BN * CH]>(smem + STAGES * AROWS * CH);
@@ -436,7 +464,122 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
   // compiler's view, so the waits for them are explicit: before the barrier
   // of step k, at most the loads of the younger steps may be outstanding
   // (vmcnt drains in issue order).
-  if constexpr (HALO) {
+  if constexpr (PP) {
+    // Two-group schedule. Waves 0-3 (group 0) and 4-7 (group 1) hold one
+    // wave of each group per SIMD; every step k is a memory phase M_k (all
+    // of the step's fragments read from LDS into registers, plus this
+    // group's share of future global->LDS loads) and a compute phase C_k
+    // (the step's MFMAs only), each ended by a workgroup barrier. Group 1
+    // runs one barrier behind group 0, so on every SIMD one wave's MFMAs
+    // overlap the other wave's LDS reads and load issue.
+    //   barrier numbers: group 0 runs M_k between barriers 2k-1 and 2k and
+    //   C_k up to 2k+1; group 1 runs M_k up to 2k+1 and C_k up to 2k+2.
+    //   Weights: group 0 issues step k+1's tile in M_k into buffer (k+1)&1,
+    //   which group 1 last read in M_{k-1} (done by barrier 2k-1), and waits
+    //   for it before barrier 2k+1, ahead of both groups' M_{k+1}.
+    //   Halo: group 1 issues the next slice's halo in the slice's first
+    //   taps-1 steps (piece i in tap step i mod (taps-1)) into the buffer
+    //   the previous slice used (last read in group 1's M of that slice's
+    //   final step), and waits for each piece before the barrier closing
+    //   its following C phase, ahead of group 0's first M of the next slice.
+    //   (Issuing the loads between the MFMA rounds of a C phase instead
+    //   measured 6 % slower.)
+    const int n_slices = a.cin_pad / BK;
+    const int grp = wave >> 2;
+    const int gw = wave & 3;             // wave within its group
+    const int gtid = tid & 255;          // thread within its group
+    const int gchunk = gtid & (CH - 1);  // this thread's physical chunk
+    constexpr int RCH = sizeof(T) == 1 ? 2 : 1;  // chunks per MFMA round
+    constexpr int NR = CH / 2 / RCH;              // rounds per step
+    constexpr int BPT = BN * CH / 256;            // weight loads of a step per group-0 thread
+    // weight rows r0 + 32 i of the B tile (r0 = gtid / CH): their XOR key
+    // does not depend on i, so one lane offset serves every load and the
+    // row and step offsets are uniform
+    const int r0 = gtid / CH;
+    const uint32_t b_voff = (uint32_t)((r0 * a.K_pad + C::logical_chunk(r0, gchunk) * VEC) * (int)sizeof(T));
+    auto brow0 = [&](int i) -> long {  // packed-weight row of B-tile row 32 i
+      const int row = 32 * i;
+      return paired ? (long)((WN == 4 ? 0 : 2 * (int)blockIdx.z) + row / TN) * a.cout_pad + row % TN
+                    : (long)(a.transposed == 1 ? (int)blockIdx.z : 0) * a.cout_pad + n0 + row;
+    };
+    // weight loads i0 .. i1-1 of step kc's tile into buffer buf
+    auto issue_b_pp = [&](int kc, int buf, int i0, int i1) {
+#pragma unroll
+      for (int i = i0; i < i1; ++i)
+        load_to_lds_s(wgt + brow0(i) * a.K_pad + (long)kc * BK, b_voff, &Bs[buf][i * 256 + gw * 64]);
+    };
+    const int n_pieces = (h_vecs + 255) / 256;
+    auto issue_halo_piece = [&](int slice, int buf, int i) {
+      const int v = gtid + i * 256;
+      const int hrow = v / CH;
+      const int hy = (hrow * hw_mul) >> 16, hx = hrow - hy * hwid;
+      const int iy = ty0 - 1 + hy, ix = tx0 - 1 + hx;
+      const bool ok = v < h_vecs && iy >= 0 && iy < a.Hi && ix >= 0 && ix < a.Wi;
+      const T* src = ok ? in_img + ((iy * a.Wi + ix) * a.in_ld + C::logical_chunk(hrow, gchunk) * VEC +
+                                    slice * BK)
+                        : zero;
+      if (v < h_vecs) load_to_lds(src, &As[buf][i * 256 + gw * 64]);
+    };
+    if (grp == 0) {
+      issue_b_pp(0, 0, 0, BPT);
+      if (nk > 1) issue_b_pp(1, 1, 0, BPT);
+    } else if (n_slices > 0) {
+      for (int i = 0; i < n_pieces; ++i) issue_halo_piece(0, 0, i);
+    }
+    wait_vm<0>();
+    __syncthreads();
+    if (grp == 1) __syncthreads();
+    const int hsteps = a.taps - 1;  // tap steps of a slice that issue halo pieces
+    for (int kc = 0; kc < nk; ++kc) {
+      const int slice = kc / a.taps, tap = kc - slice * a.taps;
+      const int buf = kc & 1, abuf = slice & 1;
+      const int hoff = tap_dy(tap) * hwid + tap_dx(tap);
+      // M_k: every fragment of the step, then this group's loads
+      uint4 fa[NR][FM][RCH], fb[NR][FN][RCH];
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int c = 0; c < RCH; ++c) {
+          const int ch = lhalf * (CH / 2) + r * RCH + c;
+#pragma unroll
+          for (int i = 0; i < FM; ++i) fa[r][i][c] = As[abuf][C::swz(arow(i, hoff), ch)];
+#pragma unroll
+          for (int j = 0; j < FN; ++j) fb[r][j][c] = Bs[buf][C::swz(wn * TN + j * 32 + lrow, ch)];
+        }
+      if (grp == 0) {
+        if (kc >= 1 && kc + 1 < nk) issue_b_pp(kc + 1, (kc + 1) & 1, 0, BPT);
+      } else if (slice + 1 < n_slices && tap < hsteps) {
+        for (int i = tap; i < n_pieces; i += hsteps) issue_halo_piece(slice + 1, (slice + 1) & 1, i);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      __syncthreads();
+      __builtin_amdgcn_sched_barrier(0);
+      // C_k: the step's MFMAs
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            if constexpr (sizeof(T) == 1) {
+              if constexpr (SW)
+                mfma_f8(acc[i][j], fb[r][j][0], fb[r][j][1], fa[r][i][0], fa[r][i][1]);
+              else
+                mfma_f8(acc[i][j], fa[r][i][0], fa[r][i][1], fb[r][j][0], fb[r][j][1]);
+            } else {
+              if constexpr (SW)
+                mfma_chunk<T>(acc[i][j], fb[r][j][0], fa[r][i][0]);
+              else
+                mfma_chunk<T>(acc[i][j], fa[r][i][0], fb[r][j][0]);
+            }
+          }
+      __builtin_amdgcn_sched_barrier(0);
+      wait_vm<0>();
+      __syncthreads();
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (grp == 0) __syncthreads();
+  } else if constexpr (HALO) {
     // two weight stages and two halo buffers; every load of step kc is
     // waited for (vmcnt 0) before the barrier of step kc + 1. Inside a step
     // the fragments of round r + 1 are read while round r's MFMAs run, and
@@ -523,6 +666,22 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
     }
   }
 
+  // Per-channel parameters of the tile's output channels pbase .. pbase+BN-1
+  // (bias, weight scale, fp8 output scale) staged once in LDS once every
+  // wave is done with the rings: one global load per thread and one wait,
+  // instead of a dependent global load per channel group in every lane.
+  const int pbase = (merged || paired) ? 0 : n0;
+  float* prm = reinterpret_cast<float*>(smem + PRM_OFF_VECS);
+  __syncthreads();
+  for (int c = tid; c < BN; c += NT) {
+    const int n = pbase + c;
+    const bool ok = n < a.cout;
+    prm[c] = ok ? a.bias[n] : 0.f;
+    prm[BN + c] = ok && a.w_scale ? a.w_scale[n] : 1.f;
+    prm[2 * BN + c] = ok && a.out_scale ? a.out_scale[n] : 1.f;
+  }
+  __syncthreads();
+
   if constexpr (!SW) {
     // Epilogue (pixels as A): lane l holds channel l%32 of fragment j for 16
     // pixels; bias, ReLU, optional accumulate, store (NHWC, channel slice).
@@ -558,8 +717,8 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
           o = n - ph * cout_m;
           col = ((long)(ph >> 1) * a.Wout + (ph & 1)) * a.out_ld + o;
         }
-        const float bn = a.bias[o];
-        const float ws = a.w_scale ? a.w_scale[o] : 1.f;
+        const float bn = prm[o - pbase];
+        const float ws = prm[BN + o - pbase];
         float amax = 0.f;
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
@@ -582,7 +741,6 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
     // per group of lanes.
     const int E = a.out_scale ? 1 : 2;  // output element bytes (fp8 or bf16)
     {
-      __syncthreads();  // every wave is done reading the A/B rings
       const int pitch = TN * E;         // bytes per pixel row of the wave tile
       const int cpr = pitch / 16;       // 16-byte chunks per row (a power of two)
       char* region = reinterpret_cast<char*>(smem) + (size_t)wave * TM * TN * 2;
@@ -594,20 +752,13 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
           const int c0 = j * 32 + 8 * g + 4 * lhalf;  // channel within the wave tile
           const int n = col0 + c0;
           const bool nok = n < a.cout;  // cout is a multiple of 8: all four or none
-          const int nb = nok ? n : 0;
-          const float4 bias4 = *reinterpret_cast<const float4*>(a.bias + nb);
-          const float4 ws4 = a.w_scale ? *reinterpret_cast<const float4*>(a.w_scale + nb)
-                                       : make_float4(1.f, 1.f, 1.f, 1.f);
+          const float* pc = prm + (n - pbase);  // in [0, BN), 16-byte aligned
+          const float4 bias4 = *reinterpret_cast<const float4*>(pc);
+          const float4 ws4 = *reinterpret_cast<const float4*>(pc + BN);
+          const float4 o4 = *reinterpret_cast<const float4*>(pc + 2 * BN);
           const float bq[4] = {bias4.x, bias4.y, bias4.z, bias4.w};
           const float sq[4] = {ws4.x, ws4.y, ws4.z, ws4.w};
-          float os[4] = {1.f, 1.f, 1.f, 1.f};
-          if (E == 1) {
-            const float4 o4 = *reinterpret_cast<const float4*>(a.out_scale + nb);
-            os[0] = o4.x;
-            os[1] = o4.y;
-            os[2] = o4.z;
-            os[3] = o4.w;
-          }
+          const float os[4] = {o4.x, o4.y, o4.z, o4.w};
 #pragma unroll
           for (int i = 0; i < FM; ++i) {
             const int p = i * 32 + lrow;
@@ -671,7 +822,8 @@ inline bool halo_tile_ok(const ConvArgs& a, int bk) {
          halo_width_ok(a.tile_w);
 }
 
-template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES, int SWZ = 0, bool HALO = false>
+template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES, int SWZ = 0, bool HALO = false,
+          bool PP = false>
 hipError_t launch_variant(const ConvArgs& a, hipStream_t s) {
   using C = Conv<T, BM, BN, WM, WN, KB, STAGES, SWZ>;
   if (HALO && !halo_tile_ok(a, C::BK)) return hipErrorInvalidValue;
@@ -696,13 +848,13 @@ hipError_t launch_variant(const ConvArgs& a, hipStream_t s) {
                       a.cout % run == 0 && a.out_ld % run == 0;
   if constexpr (sizeof(T) != 4 && BN >= 128) {
     if (staged) {
-      hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES, SWZ, true, HALO>), grid, dim3(C::NT), 0,
-                         s, a);
+      hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES, SWZ, true, HALO, PP>), grid, dim3(C::NT),
+                         0, s, a);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES, SWZ, false, HALO>), grid, dim3(C::NT), 0, s,
-                     a);
+  hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES, SWZ, false, HALO, PP>), grid, dim3(C::NT), 0,
+                     s, a);
   return hipGetLastError();
 }
 

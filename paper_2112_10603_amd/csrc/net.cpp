@@ -1274,9 +1274,9 @@ Status Net::autotune(const float* const* left, const float* const* right, int n_
   FFV_TRY(check(hipEventCreate(&e0), "hipEventCreate"));
   Status res = check(hipEventCreate(&e1), "hipEventCreate");
   std::map<TuneKey, TuneVal> found;
-  const ConvTile tiles[13] = {ConvTile::N256, ConvTile::N128, ConvTile::N64,  ConvTile::N32, ConvTile::H32,
+  const ConvTile tiles[14] = {ConvTile::N256, ConvTile::N128, ConvTile::N64,  ConvTile::N32, ConvTile::H32,
                               ConvTile::H256, ConvTile::H128, ConvTile::R32,  ConvTile::R64, ConvTile::S32,
-                              ConvTile::S64,  ConvTile::S128, ConvTile::Q256};
+                              ConvTile::S64,  ConvTile::S128, ConvTile::Q256, ConvTile::P256};
   const int widths[4] = {8, 16, 32, 64};
   for (size_t r = 0; res.good() && r < recs_.size(); ++r) {
     const TuneRec& rec = recs_[r];
@@ -1290,16 +1290,18 @@ Status Net::autotune(const float* const* left, const float* const* right, int n_
     }
     float best_ms = -1.f;
     TuneVal best{};
-    for (int ti = 0; res.good() && ti < 13; ++ti) {
+    for (int ti = 0; res.good() && ti < 14; ++ti) {
       const bool resident = tiles[ti] == ConvTile::R32 || tiles[ti] == ConvTile::R64;
       const bool s2 = tiles[ti] == ConvTile::S32 || tiles[ti] == ConvTile::S64 || tiles[ti] == ConvTile::S128;
       const bool halo = tiles[ti] == ConvTile::H32 || resident || s2;
-      const bool halo_big = tiles[ti] == ConvTile::H256 || tiles[ti] == ConvTile::H128 || tiles[ti] == ConvTile::Q256;
+      const bool halo_big = tiles[ti] == ConvTile::H256 || tiles[ti] == ConvTile::H128 || tiles[ti] == ConvTile::Q256 ||
+                            tiles[ti] == ConvTile::P256;
       const int bn = conv_tile_bn(tiles[ti]);
       // at least half of every tile's columns real (a 256-column halo tile
       // over a per-phase transposed conv holds two, or with 2 x 4 waves
       // four, phases)
-      const bool paired = rec.a.transposed == 1 && ((tiles[ti] == ConvTile::H256 && rows32 <= 128) ||
+      const bool halo256 = tiles[ti] == ConvTile::H256 || tiles[ti] == ConvTile::P256;
+      const bool paired = rec.a.transposed == 1 && ((halo256 && rows32 <= 128) ||
                                                     (tiles[ti] == ConvTile::Q256 && rows32 <= 64));
       if (bn >= 2 * rows32 && !paired) continue;
       // the 2 x 4-wave layout only where it groups four phases
@@ -1352,6 +1354,7 @@ static std::string tile_name(ConvTile t) {
   if (t == ConvTile::R32 || t == ConvTile::R64) return "r" + n;
   if (t == ConvTile::S32 || t == ConvTile::S64 || t == ConvTile::S128) return "s" + n;
   if (t == ConvTile::Q256) return "q256";
+  if (t == ConvTile::P256) return "p256";
   return (t == ConvTile::H32 || t == ConvTile::H256 || t == ConvTile::H128) ? "h" + n : n;
 }
 
@@ -1398,6 +1401,7 @@ Status Net::load_tuning(const std::string& path, int* n_loaded) {
     else if (tn == "h256" && (tw == 8 || tw == 16 || tw == 32)) t = ConvTile::H256;
     else if (tn == "h128" && (tw == 8 || tw == 16 || tw == 32)) t = ConvTile::H128;
     else if (tn == "q256" && (tw == 8 || tw == 16 || tw == 32)) t = ConvTile::Q256;
+    else if (tn == "p256" && (tw == 8 || tw == 16 || tw == 32)) t = ConvTile::P256;
     else if (tn == "r32" && tw == 16) t = ConvTile::R32;
     else if (tn == "r64" && tw == 16) t = ConvTile::R64;
     else if (tn == "s32" && tw == 16) t = ConvTile::S32;

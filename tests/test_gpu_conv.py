@@ -141,7 +141,7 @@ def test_conv_tile_variants_agree(cin, cout, h, w, stride, transposed):
             assert torch.equal(got, base), ("resident", bn, (got - base).abs().max().item())
     if (transposed or stride == 1) and cin % 64 == 0:
         per_phase = transposed and cout > 16
-        codes = (2, 3) + ((9,) if not per_phase or cout <= 64 else ())
+        codes = (2, 3, 10) + ((9,) if not per_phase or cout <= 64 else ())
         if per_phase and cout > 128:
             codes = (2,)
         for code in codes:  # 128- and 256-channel halo tiles, 2 x 4-wave layout
@@ -218,7 +218,7 @@ def test_conv_halo_tiles_vs_oracle(cin, cout, h, w, transposed, precision):
     rng = np.random.default_rng(cin * 13 + cout + h)
     n = 2
     per_phase = transposed and cout > 16
-    codes = (2, 3) + ((9,) if not per_phase or cout <= 64 else ())
+    codes = (2, 3, 10) + ((9,) if not per_phase or cout <= 64 else ())
     x = rng.standard_normal((n, cin, h, w)).astype(np.float32)
     if transposed:
         wt = (rng.standard_normal((cin, cout, 4, 4)) / np.sqrt(4 * cin)).astype(np.float32)
@@ -257,6 +257,10 @@ def test_conv_halo_tile_rejects_other_layers():
         op_conv(x, wt, b, stride=2, precision="bf16", n_tile=3, tile_w=16)
     with pytest.raises(FfvError):
         op_conv(x, wt, b, stride=1, precision="bf16", n_tile=3, tile_w=64)
+    with pytest.raises(FfvError):
+        op_conv(x, wt, b, stride=2, precision="bf16", n_tile=10, tile_w=16)
+    with pytest.raises(FfvError):
+        op_conv(x, wt, b, stride=1, precision="bf16", n_tile=10, tile_w=64)
 
 
 RESIDENT_CASES = [
@@ -351,6 +355,9 @@ STAGED_CASES = [
     (2, 128, 40, 11, 19, 0, True, 3, 8),
     (2, 256, 64, 13, 17, 0, True, 9, 16),
     (2, 64, 256, 21, 35, 1, False, 9, 32),
+    (2, 256, 256, 19, 37, 1, False, 10, 16),
+    (2, 128, 128, 13, 22, 0, True, 10, 8),
+    (2, 64, 40, 11, 19, 0, True, 10, 32),
 ]
 
 

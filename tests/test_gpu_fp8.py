@@ -70,10 +70,19 @@ def test_fp8_batch_invariance(wfile):
     net.close()
 
 
+# e4m3 keeps 3 mantissa bits (unit roundoff 2^-4), bf16 7 (2^-8). To first
+# order the output error is linear in the rounding errors, so moving the
+# VIBlock convs from bf16 to fp8 can raise the MSE by at most
+# (2^-4 / 2^-8)^2 = 256 (24.08 dB); a factor 2 (3.01 dB) more covers values
+# beyond the calibrated range, which saturate.
+FP8_PSNR_DROP_DB = 27.09
+
+
 def test_fp8_error_vs_oracle(wfile):
-    """Report FP8 PSNR against the FP64 oracle on a 256x256 crop of the
-    1080p arc (calibrated on a different seeded scene); the bound is loose:
-    fp8 e4m3 carries 3 mantissa bits."""
+    """FP8 error against the FP64 oracle on a 256x256 crop of the 1080p arc
+    (calibrated on a different seeded scene), bounded by the BF16 path's
+    error on the same crop and the two formats' unit roundoffs."""
+    from paper_2112_10603_amd import Net
     print("case fp8 psnr", flush=True)
     arc = scenes.hd_arc(2)
     xl = arc[0, :, 300:556, 800:1056].contiguous()
@@ -81,8 +90,13 @@ def test_fp8_error_vs_oracle(wfile):
     cal = scenes.hd_arc(2, seed=99)
     net = _fp8_net(wfile, (cal[0, :, 0:256, 0:256].contiguous(), cal[1, :, 0:256, 0:256].contiguous()))
     out = net.interpolate([(xl.to(DEV), xr.to(DEV))], [0.5])[0, 0].cpu().numpy()
-    ref = O.vinet_forward(xl.numpy(), xr.numpy(), 0.5, O.load_weights(wfile))
-    p = psnr(out, ref)
-    print(f"  FP8 PSNR vs oracle {p:.2f} dB, max-abs {np.abs(out - ref).max():.3e}")
-    assert p >= 25.0
     net.close()
+    net16 = Net(wfile, "bf16", 0)
+    out16 = net16.interpolate([(xl.to(DEV), xr.to(DEV))], [0.5])[0, 0].cpu().numpy()
+    net16.close()
+    ref = O.vinet_forward(xl.numpy(), xr.numpy(), 0.5, O.load_weights(wfile))
+    p8, p16 = psnr(out, ref), psnr(out16, ref)
+    print(f"  FP8 PSNR vs oracle {p8:.2f} dB, max-abs {np.abs(out - ref).max():.3e}; "
+          f"BF16 {p16:.2f} dB, max-abs {np.abs(out16 - ref).max():.3e}")
+    assert p16 >= 45.0
+    assert p8 >= p16 - FP8_PSNR_DROP_DB

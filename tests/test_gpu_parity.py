@@ -176,6 +176,23 @@ def test_chunked_workspace_matches(wfile):
     assert torch.equal(full, small)
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("t", [0.25, 8 / 17])
+def test_fp32_full_1080p_parity(wfile, oracle_w, t):
+    """The plain FP32 path on the full 1080x1920 pair (disparity 0-48 px,
+    padded to 1088 rows inside) against the FP64 oracle: max-abs <= 1e-4 on
+    every output value."""
+    print(f"case fp32 1080p t={t:.4f}", flush=True)
+    arc = scenes.hd_arc(2)
+    net = _net(wfile, workspace_bytes=16 << 30)
+    out = net.interpolate([(arc[0].to(DEV), arc[1].to(DEV))], [t])[0, 0].cpu().numpy()
+    net.close()
+    ref = O.vinet_forward(arc[0].numpy(), arc[1].numpy(), t, oracle_w)
+    e = float(np.abs(out.astype(np.float64) - ref).max())
+    print(f"  max-abs {e:.3e}, PSNR {psnr(out, ref):.2f} dB", flush=True)
+    assert e <= 1e-4
+
+
 def test_bf16_psnr_small(wfile, oracle_w):
     print("case bf16 psnr 128", flush=True)
     xl, xr = scenes.small_pair()
