@@ -331,6 +331,34 @@ def fp8_4k_leg(wpath, dev, reps=3, with_oracle=True, crops_per_pair=4):
     return res
 
 
+def lap_loss_leg(views, gt, reps=10):
+    """The Eq. 3 Laplacian-pyramid loss (training side) on a batch of
+    synthesised views against a reference image: forward only, and forward
+    with the gradient; milliseconds per view and GB/s against the algorithmic
+    bytes (read both images once; write the gradient once)."""
+    import torch
+
+    from paper_2112_10603_amd import lap_loss
+
+    n, _, H, W = views.shape
+    res = {"views": n, "size": f"{H}x{W}"}
+    for grad in (False, True):
+        lap_loss(views, gt, grad=grad)
+        s = torch.cuda.current_stream(views.device)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            lap_loss(views, gt, grad=grad)
+        e1.record(s)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        nbytes = n * 3 * H * W * 4 * (3 if grad else 2)
+        key = "loss_and_grad" if grad else "loss"
+        res[key] = {"ms_per_view": round(ms / n, 4), "gbs_algorithmic": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                    "note": "includes the call's workspace allocation and stream synchronisation"}
+    return res
+
+
 def next_leg(wpath, dev, reps=5):
     """The paper's two other inference modes, timed on the GPU beside the
     direct t-plane path (BF16, batch of one pair, inputs resident):
@@ -552,6 +580,10 @@ def main():
     # one BF16 view kept for the PSNR check: pair 0, t = 8/17
     j_ref = len(ts) // 2 - 1
     bf16_view = out[0, j_ref].cpu().numpy()
+    # the training-side loss of Eq. 3 over pair 0's views against camera 1
+    lap = None
+    if H >= 33 and W >= 33:
+        lap = lap_loss_leg(out[0].contiguous(), arc[1].expand(len(ts), -1, -1, -1).contiguous())
     net.close()
     del out
 
@@ -676,6 +708,7 @@ def main():
         "inference_modes": modes,
         "pixel_passes": pixel_passes,
         "cluster_stitch": stitch,
+        "lap_loss_eq3": lap,
         "bf16_vs_fp32": None if fp32 is None else round(value / fp32["views_per_s"], 2),
         "conv_mfma_util": round(conv_flops / (conv_ms * 1e-3) / 1e12 / PEAK_BF16_TFLOPS, 4)
         if conv_ms > 0 else None,

@@ -351,6 +351,31 @@ ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, int32_t cin
                        int32_t stride, int32_t transposed, int32_t relu, int32_t n_tile,
                        int32_t tile_w, float* y, void* stream);
 
+/*
+ * Laplacian-pyramid colour loss of the training objective (section 3.1,
+ * "Loss functions", Eq. 3) and, optionally, its gradient with respect to the
+ * synthesised images:
+ *   loss[i] = sum_{k=1..5} 2^(k-1) * mean |L^k(x_i) - L^k(gt_i)|
+ * where L^k is the k-th band-pass level of a Laplacian pyramid. The paper
+ * does not define the pyramid; the library's reading: the separable
+ * binomial filter [1, 4, 6, 4, 1] / 16 with mirror padding (edge sample not
+ * repeated), reduce = even samples of the blurred level, expand = the
+ * zero-inserted coarser level blurred with gain 2 per axis, band
+ * L^k = G^k - expand(G^(k+1)) (the low-pass residual is not a term), and the
+ * mean taken over all 3 * h_k * w_k values of a level.
+ *   x, gt: DEVICE float32 planar [n][3][H][W] (synthesised view, ground truth)
+ *   loss:  DEVICE float32 [n]
+ *   grad:  DEVICE float32 [n][3][H][W] = d loss[i] / d x_i, or NULL; at a
+ *          sample where a band is exactly 0 the sign is taken as 0
+ * H, W >= 33 (five levels of mirror padding need 3 samples at the coarsest).
+ * Allocates its workspace, orders its work on `stream` (NULL = default
+ * stream) and synchronises it. Per-workgroup sums are combined in a fixed
+ * order in double precision, so repeated calls give identical results.
+ * Errors: FFV_ERR_ARG, FFV_ERR_OOM, FFV_ERR_DEVICE.
+ */
+ffv_status ffv_lap_loss(const float* x, const float* gt, int32_t n, int32_t height, int32_t width,
+                        float* loss, float* grad, void* stream);
+
 /* Bytes of the per-device scratch array behind ffv_op_conv_noalloc. */
 #define FFV_OP_NOALLOC_SCRATCH_BYTES (64u << 20)
 

@@ -3,4 +3,4 @@
 The compute path is ``lib/libffv.so`` (HIP kernels for gfx950 behind the C
 ABI of ``include/ffv.h``); :mod:`.ffv` marshals torch device tensors into it.
 """
-from .ffv import FfvError, Net, debug_fault, lib, op_conv, stitch_cluster  # noqa: F401
+from .ffv import FfvError, Net, debug_fault, lap_loss, lib, op_conv, stitch_cluster  # noqa: F401

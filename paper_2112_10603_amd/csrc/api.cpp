@@ -7,6 +7,7 @@
 
 #include "../../include/ffv.h"
 #include "fault.h"
+#include "lap.h"
 #include "net.h"
 #include "op_conv.h"
 
@@ -491,4 +492,26 @@ extern "C" ffv_status ffv_op_conv(int32_t precision, const float* x, int32_t n, 
                                   int32_t n_tile, int32_t tile_w, float* y, void* stream) {
   return ffv::op_conv_run(nullptr, precision, x, n, cin, h, w, weight, bias, cout, stride, transposed, relu,
                           n_tile, tile_w, y, stream);
+}
+
+extern "C" ffv_status ffv_lap_loss(const float* x, const float* gt, int32_t n, int32_t height, int32_t width,
+                                   float* loss, float* grad, void* stream) {
+  using namespace ffv;
+  if (!x || !gt || !loss) return fail(FFV_ERR_ARG, "null argument");
+  if (n <= 0) return fail(FFV_ERR_ARG, "n must be positive");
+  if (height < kLapMinSize || width < kLapMinSize)
+    return fail(FFV_ERR_ARG, "height and width must be >= " + std::to_string(kLapMinSize));
+  if ((long)height * width > (1L << 28)) return fail(FFV_ERR_ARG, "image too large");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t bytes = lap_workspace_bytes(n, height, width, grad != nullptr);
+  void* ws = nullptr;
+  if (fault_hit("alloc") || hipMalloc(&ws, bytes) != hipSuccess) return fail(FFV_ERR_OOM, "workspace");
+  hipError_t err = launch_lap_loss(x, gt, n, height, width, loss, grad, ws, bytes, s);
+  // wait before freeing: queued kernels read the workspace
+  const hipError_t sync = hipStreamSynchronize(s);
+  if (err == hipSuccess) err = sync;
+  hipFree(ws);
+  if (err != hipSuccess) return fail(FFV_ERR_DEVICE, hipGetErrorString(err));
+  g_last_error.clear();
+  return FFV_OK;
 }

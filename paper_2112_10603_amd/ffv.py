@@ -29,7 +29,8 @@ EXPORTS = ["ffv_default_opts", "ffv_create_net", "ffv_destroy_net", "ffv_interpo
            "ffv_last_error", "ffv_calibrate", "ffv_register_camera", "ffv_submit", "ffv_poll", "ffv_serving_stats",
            "ffv_debug_tap", "ffv_set_debug", "ffv_set_profiling", "ffv_kernel_stats", "ffv_op_conv",
            "ffv_autotune", "ffv_save_tuning", "ffv_load_tuning", "ffv_interpolate_blend",
-           "ffv_interpolate_recursive", "ffv_stitch_cluster", "ffv_debug_fault", "ffv_op_conv_noalloc"]
+           "ffv_interpolate_recursive", "ffv_stitch_cluster", "ffv_debug_fault", "ffv_op_conv_noalloc",
+           "ffv_lap_loss"]
 FFV_OP_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
@@ -99,6 +100,8 @@ def lib() -> ctypes.CDLL:
     L.ffv_op_conv.restype = c_int
     L.ffv_op_conv_noalloc.argtypes = L.ffv_op_conv.argtypes
     L.ffv_op_conv_noalloc.restype = c_int
+    L.ffv_lap_loss.argtypes = [c_void, c_void, c_int, c_int, c_int, c_void, c_void, c_void]
+    L.ffv_lap_loss.restype = c_int
     L.ffv_autotune.argtypes = [c_void, ctypes.POINTER(ffv_pair), c_int, ctypes.POINTER(c_f), c_int,
                                c_void, ctypes.POINTER(c_int)]
     L.ffv_autotune.restype = c_int
@@ -356,6 +359,23 @@ def op_conv(x: torch.Tensor, weight, bias, stride: int = 1, transposed: bool = F
               wt.ctypes.data, bs.ctypes.data, cout, stride, 1 if transposed else 0,
               1 if relu else 0, n_tile, tile_w, y.data_ptr(), s.cuda_stream))
     return y
+
+
+def lap_loss(x: torch.Tensor, gt: torch.Tensor, grad: bool = False):
+    """Eq. 3 Laplacian-pyramid loss of each image in ``x`` against ``gt``
+    ([n, 3, H, W] float32 CUDA): a float32 tensor [n], and with ``grad`` also
+    d loss / d x [n, 3, H, W]."""
+    _dev_f32(x, "x")
+    _dev_f32(gt, "gt")
+    if x.dim() != 4 or x.shape[1] != 3 or x.shape != gt.shape:
+        raise ValueError("x and gt must both be [n, 3, H, W]")
+    n, _, H, W = x.shape
+    loss = torch.empty(n, dtype=torch.float32, device=x.device)
+    g = torch.empty_like(x) if grad else None
+    s = torch.cuda.current_stream(x.device)
+    _check(lib().ffv_lap_loss(x.data_ptr(), gt.data_ptr(), n, H, W, loss.data_ptr(),
+                              g.data_ptr() if grad else None, s.cuda_stream))
+    return (loss, g) if grad else loss
 
 
 def stitch_cluster(real_view: torch.Tensor, left, right, out: torch.Tensor | None = None) -> torch.Tensor:
