@@ -265,6 +265,69 @@ def serve_leg(wpath, dev, seconds, rate_fraction=None, capacity=None, users=64, 
             "budget_gib": budget >> 30, "tick_ms": tick_ms}
 
 
+PEAK_FP8_TFLOPS = 5000.0
+
+
+def fp8_calibrated_net(wpath, dev, workspace_bytes):
+    """An FP8 net calibrated on a 256x256 crop of a separately seeded 4K
+    scene (seed 99), t = 1/2."""
+    from paper_2112_10603_amd import Net
+    from synth import scenes
+    cal = scenes.uhd_arc(2, seed=99, device=dev)
+    net = Net(wpath, "fp8", 0, workspace_bytes=workspace_bytes)
+    net.calibrate(cal[0, :, 1000:1256, 1800:2056].contiguous(),
+                  cal[1, :, 1000:1256, 1800:2056].contiguous(), 0.5)
+    return net
+
+
+def conv_roofline(stats, steps):
+    """conv256 class and all-conv TFLOP/s from the library's per-class HIP
+    event timing, against the FP8 dense peak."""
+    out = {}
+    c = stats["conv256"]
+    if c["ms"] > 0:
+        tf = c["work"] / (c["ms"] * 1e-3) / 1e12
+        out["conv256"] = {"avg_launch_ms": round(c["ms"] / c["launches"], 4), "tflops": round(tf, 1),
+                          "frac_of_fp8_peak": round(tf / PEAK_FP8_TFLOPS, 4)}
+    ms = sum(stats[k]["ms"] for k in ("conv256", "conv", "convT"))
+    work = sum(stats[k]["work"] for k in ("conv256", "conv", "convT"))
+    if ms > 0:
+        out["all_convs"] = {"ms_per_step": round(ms / steps, 3), "tflops": round(work / (ms * 1e-3) / 1e12, 1)}
+    return out
+
+
+def fp8_dense_leg(wpath, dev, pairs, ts, steps=5, warmup=2):
+    """FP8 on the dense 1080p batch (the same 112 views as the headline
+    step): calibrated as the 4K leg, conv tiles autotuned in FP8, views/s and
+    the conv classes' TFLOP/s against the FP8 peak. Returns the result and
+    pair 0's view at the oracle check's phase."""
+    import torch
+    net = fp8_calibrated_net(wpath, dev, 128 << 30)
+    H, W = pairs[0][0].shape[1:]
+    out = torch.empty((len(pairs), len(ts), 3, H, W), dtype=torch.float32, device=dev)
+    net.autotune(pairs, ts, out)
+    net.set_profiling(True)
+    for _ in range(warmup):
+        net.interpolate(pairs, ts, out)
+    torch.cuda.synchronize()
+    net.set_profiling(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.interpolate(pairs, ts, out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    stats = {k: net.kernel_stats(k) for k in ("conv256", "conv", "convT")}
+    net.set_profiling(False)
+    view = out[0, len(ts) // 2 - 1].cpu().numpy()
+    n = len(pairs) * len(ts)
+    res = {"views_per_s": round(n / dt, 2), "ms_per_step": round(1000 * dt, 2), "views_per_step": n,
+           "workload": f"the dense batch ({n} views of {H}x{W}); VIBlock 128/256-ch convs fp8 e4m3, "
+                       "other convs bf16; tiles autotuned in fp8",
+           "conv_roofline": conv_roofline(stats, steps)}
+    net.close()
+    return res, view
+
+
 def fp8_4k_leg(wpath, dev, reps=3, with_oracle=True, crops_per_pair=4):
     """FP8 at 4K: 4 independent pairs of 3x2160x3840 (disparity 0..96 px),
     t = 0.5, one call for all four; FP8 e4m3 VIBlock convs calibrated on a
@@ -279,23 +342,25 @@ def fp8_4k_leg(wpath, dev, reps=3, with_oracle=True, crops_per_pair=4):
     from synth import scenes
 
     pairs = [scenes.uhd_arc(2, seed=40 + i, device=dev) for i in range(4)]
-    cal = scenes.uhd_arc(2, seed=99, device=dev)
-    net = Net(wpath, "fp8", 0, workspace_bytes=64 << 30)
-    net.calibrate(cal[0, :, 1000:1256, 1800:2056].contiguous(),
-                  cal[1, :, 1000:1256, 1800:2056].contiguous(), 0.5)
-    del cal
+    net = fp8_calibrated_net(wpath, dev, 64 << 30)
     pv = [(p[0], p[1]) for p in pairs]
     out = torch.empty((4, 1, 3, 2160, 3840), dtype=torch.float32, device=dev)
+    net.autotune(pv, [0.5], out)
+    net.set_profiling(True)
     net.interpolate(pv, [0.5], out)
     torch.cuda.synchronize()
+    net.set_profiling(True)
     t0 = time.perf_counter()
     for _ in range(reps):
         net.interpolate(pv, [0.5], out)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
+    stats = {k: net.kernel_stats(k) for k in ("conv256", "conv", "convT")}
+    net.set_profiling(False)
     res = {"views_per_s": round(4 / dt, 2), "ms_per_call": round(1000 * dt, 2),
            "workload": "4 pairs 2160x3840, t=0.5, one call; VIBlock 128/256-ch convs fp8 e4m3 "
-                       "(per-channel scales), other convs bf16"}
+                       "(per-channel scales), other convs bf16; tiles autotuned in fp8",
+           "conv_roofline": conv_roofline(stats, reps)}
     if with_oracle:
         from oracle import vinet as oracle
         Wo = oracle.load_weights(wpath)
@@ -642,6 +707,12 @@ def main():
         fp8 = fp8_4k_leg(wpath, dev, with_oracle=not args.no_oracle)
         print(f"[bench] fp8 4K: {fp8['views_per_s']} views/s", file=sys.stderr, flush=True)
 
+    fp8_dense = None
+    fp8_dense_view = None
+    if not args.no_fp8:
+        fp8_dense, fp8_dense_view = fp8_dense_leg(wpath, dev, pairs, ts)
+        print(f"[bench] fp8 dense: {fp8_dense['views_per_s']} views/s", file=sys.stderr, flush=True)
+
     modes = None
     if not args.no_next:
         modes = next_leg(wpath, dev)
@@ -670,6 +741,8 @@ def main():
             accuracy["fp32"] = error_stats(fp32_view, ref)
             accuracy["fp32"]["target_max_abs"] = 1e-4
             accuracy["fp32"]["target_met"] = accuracy["fp32"]["max_abs"] <= 1e-4
+        if fp8_dense_view is not None:
+            accuracy["fp8"] = error_stats(fp8_dense_view, ref)
         accuracy["bf16"]["target_psnr_db"] = 45.0
         accuracy["bf16"]["target_met"] = accuracy["bf16"]["psnr_db"] >= 45.0
         psnr = accuracy["bf16"]["psnr_db"]
@@ -705,6 +778,7 @@ def main():
         "fp32_plain": fp32,
         "serving": serving,
         "fp8_4k": fp8,
+        "fp8_dense_1080p": fp8_dense,
         "inference_modes": modes,
         "pixel_passes": pixel_passes,
         "cluster_stitch": stitch,

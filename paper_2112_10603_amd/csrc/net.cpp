@@ -575,6 +575,29 @@ Status Net::kernel_stats(const std::string& name, long* launches, double* ms, do
   return Status::ok();
 }
 
+namespace {
+
+// Block width (32, 16 or 8) of the halo tiles with the least padded area for
+// a launch, or 0 when the halo tiles cannot run it.
+int halo_default_width(DType dt, const ConvArgs& a0) {
+  int best = 0;
+  long best_area = -1;
+  for (int tw : {32, 16, 8}) {
+    ConvArgs a = a0;
+    a.tile_w = tw;
+    if (!conv_halo_tile_ok(dt, a)) continue;
+    const int th = 256 / tw;
+    const long area = (long)((a.Ho + th - 1) / th) * th * ((a.Wo + tw - 1) / tw) * tw;
+    if (best_area < 0 || area < best_area) {
+      best_area = area;
+      best = tw;
+    }
+  }
+  return best;
+}
+
+}  // namespace
+
 Status Net::conv(const Exec& x, const Layer& L, const void* in, int in_ld, long in_img_stride,
                  int Hi, int Wi, int n_img, void* out, int out_ld, long out_img_stride,
                  bool out_f32, bool accumulate, bool relu, bool in_fp8, bool out_fp8) {
@@ -628,6 +651,12 @@ Status Net::conv(const Exec& x, const Layer& L, const void* in, int in_ld, long 
   } else if (L.rows <= 32 && conv_halo_ok(kdt, a)) {
     tile = ConvTile::H32;
     a.tile_w = 16;
+  } else if (!L.transposed && kdt != DType::F32 && L.rows > 128 && halo_default_width(kdt, a) > 0) {
+    // 3x3 stride-1 convs with more than 128 outputs (the 256-channel chains):
+    // the two-group halo tile, the fastest tile for them when tuned, at the
+    // least padded block width it accepts
+    tile = ConvTile::P256;
+    a.tile_w = halo_default_width(kdt, a);
   } else if (!L.transposed && !out_f32 && L.rows <= 128) {
     // convs over a few input channels (8 to 32): the persistent kernel with
     // resident weights, narrowest N tile that holds the layer

@@ -9,6 +9,7 @@
 //
 // usage: ffv_drive WEIGHTS [precision=1] [H=1080] [W=1920] [n_cams=8] [n_t=16] [reps=1]
 //                  [tuning_file]
+// (precision 2, FP8, calibrates on the first pair at t = 1/2 before the runs)
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -103,6 +104,16 @@ int main(int argc, char** argv) {
       return 1;
     }
     std::printf("loaded %d conv tile choices from %s\n", n_loaded, argv[8]);
+  }
+  if (precision == 2) {
+    // FP8 nets quantise after a calibration pass: the first pair at t = 1/2
+    ffv_pair cal = {cams, cams + img, H, W};
+    if (ffv_calibrate(net, &cal, 0.5f) != FFV_OK) {
+      std::fprintf(stderr, "ffv_calibrate: %s\n", ffv_last_error());
+      ffv_destroy_net(net);
+      return 1;
+    }
+    std::printf("calibrated on the first pair at t = 0.5\n");
   }
   std::vector<ffv_pair> pairs(n_pairs);
   for (int i = 0; i < n_pairs; ++i) pairs[i] = {cams + i * img, cams + (i + 1) * img, H, W};
