@@ -328,7 +328,7 @@ def fp8_dense_leg(wpath, dev, pairs, ts, steps=5, warmup=2):
     return res, view
 
 
-def fp8_4k_leg(wpath, dev, reps=3, with_oracle=True, crops_per_pair=4):
+def fp8_4k_leg(wpath, dev, reps=3, with_oracle=True, crops_per_pair=4, tune_file=None):
     """FP8 at 4K: 4 independent pairs of 3x2160x3840 (disparity 0..96 px),
     t = 0.5, one call for all four; FP8 e4m3 VIBlock convs calibrated on a
     256x256 crop of a separately seeded 4K scene. Error against the FP64
@@ -345,7 +345,12 @@ def fp8_4k_leg(wpath, dev, reps=3, with_oracle=True, crops_per_pair=4):
     net = fp8_calibrated_net(wpath, dev, 64 << 30)
     pv = [(p[0], p[1]) for p in pairs]
     out = torch.empty((4, 1, 3, 2160, 3840), dtype=torch.float32, device=dev)
-    net.autotune(pv, [0.5], out)
+    if tune_file and os.path.exists(tune_file):
+        net.load_tuning(tune_file)
+    else:
+        net.autotune(pv, [0.5], out)
+        if tune_file:
+            net.save_tuning(tune_file)
     net.set_profiling(True)
     net.interpolate(pv, [0.5], out)
     torch.cuda.synchronize()
@@ -487,7 +492,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip conv tile autotuning")
     ap.add_argument("--no-next", action="store_true", help="skip the w/o-refine and recursive leg")
     ap.add_argument("--fp8-only", action="store_true",
-                    help="run only the FP8 4K leg (no JSON line; for profiling)")
+                    help="run only the FP8 4K leg (its own JSON line, no oracle; for profiling); "
+                         "--tune-file then names the FP8 tuning table")
     ap.add_argument("--tune-file", default=None,
                     help="load the conv tuning table from this file if it exists, else tune and "
                          "save it there")
@@ -511,7 +517,7 @@ def main():
     if args.fp8_only:
         td = tempfile.mkdtemp()
         wpath = write_weights_file(os.path.join(td, "w.ffvw"), seed=0)
-        print(json.dumps(fp8_4k_leg(wpath, dev, with_oracle=False)), flush=True)
+        print(json.dumps(fp8_4k_leg(wpath, dev, with_oracle=False, tune_file=args.tune_file)), flush=True)
         return
     if args.copy_calib:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)

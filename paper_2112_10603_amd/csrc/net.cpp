@@ -460,6 +460,7 @@ ViewPlan Net::view_plan(const Geo& g, int n_view) const {
 }
 
 void Net::drop_graphs() {
+  graph_epoch_.fetch_add(1, std::memory_order_acq_rel);
   for (auto& kv : graph_cache_) {
     hipGraphExecDestroy(kv.second.exec);
     for (auto& pe : kv.second.prof) {
@@ -1219,6 +1220,7 @@ Status Net::calibrate(const float* left, const float* right, int H, int W, float
     }
   FFV_TRY(quantize_vib_layers());
   calibrated_ = true;
+  drop_graphs();  // captured with the previous weights and scales
   return Status::ok();
 }
 

@@ -135,6 +135,11 @@ class Net {
   Status load_tuning(const std::string& path, int* n_loaded);
   DType dtype() const { return dt_; }
   int device() const { return device_; }
+  // Whether launch sequences may be captured into graphs and replayed, and
+  // a counter that changes whenever captured graphs become stale (tile
+  // tuning, FP8 quantisation, the workspace, the graph switch itself).
+  bool graphs_enabled() const { return graphs_ && !calibrating_ && !recording_; }
+  uint64_t graph_epoch() const { return graph_epoch_.load(std::memory_order_acquire); }
   hipStream_t stream() const { return stream_; }
 
   // serving
@@ -226,6 +231,7 @@ class Net {
     std::vector<PendingEvt> prof;
   };
   bool graphs_ = true;
+  std::atomic<uint64_t> graph_epoch_{0};
   std::map<GraphKey, GraphEntry> graph_cache_;
   void add_stat(const PendingEvt& pe);
 

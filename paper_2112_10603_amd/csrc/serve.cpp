@@ -3,16 +3,27 @@
 // batch of views, completed by a host function queued behind them.
 #include "serve.h"
 
+#include <map>
+#include <tuple>
+
 #include "fault.h"
 
 namespace ffv {
 
 namespace {
 
+// A slot's captured batches: one graph per (height, width, views), valid
+// for the slot's current workspace and the net's graph epoch.
 struct HSlot {
   hipStream_t s = nullptr;
   char* ws = nullptr;
   size_t bytes = 0;
+  uint64_t epoch = 0;
+  std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
+  void drop_graphs() {
+    for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
+    graphs.clear();
+  }
 };
 
 }  // namespace
@@ -97,6 +108,7 @@ Status HipExecutor::slot_create(size_t bytes, void** slot) {
 Status HipExecutor::slot_resize(void* slot, size_t bytes) {
   HSlot* h = static_cast<HSlot*>(slot);
   hipSetDevice(net_->device());
+  h->drop_graphs();  // they address the old workspace
   if (h->ws) hipFree(h->ws);
   h->ws = nullptr;
   h->bytes = 0;
@@ -109,6 +121,7 @@ void HipExecutor::slot_destroy(void* slot) {
   HSlot* h = static_cast<HSlot*>(slot);
   hipSetDevice(net_->device());
   if (h->s) hipStreamSynchronize(h->s);
+  h->drop_graphs();
   if (h->ws) hipFree(h->ws);
   if (h->s) hipStreamDestroy(h->s);
   delete h;
@@ -138,7 +151,42 @@ Status HipExecutor::launch(void* slot, int H, int W, const ViewJob* jobs, int n,
   Exec x;
   x.s = h->s;
   x.ws = h->ws;
-  Status st = net_->run_views(x, vp, cam_table_, vd.data(), n);
+  Status st;
+  if (net_->graphs_enabled()) {
+    // The batch's view descriptors go to the slot's device table first, so a
+    // captured graph holds no per-request value and replays for any batch of
+    // the same shape on this slot.
+    ViewDesc* tab = (ViewDesc*)x.at(vp.views);
+    st = net_->check(hipMemcpyAsync(tab, vd.data(), sizeof(ViewDesc) * n, hipMemcpyHostToDevice, h->s),
+                     "copy views");
+    const uint64_t epoch = net_->graph_epoch();
+    if (h->epoch != epoch) {
+      h->drop_graphs();
+      h->epoch = epoch;
+    }
+    const auto key = std::make_tuple(H, W, n);
+    auto it = h->graphs.find(key);
+    if (st.good() && it == h->graphs.end()) {
+      if (h->graphs.size() >= 128) h->drop_graphs();  // bound the cache (batch shapes vary)
+      st = net_->check(hipStreamBeginCapture(h->s, hipStreamCaptureModeThreadLocal), "begin capture");
+      if (st.good()) {
+        x.capture = true;
+        Status run = net_->run_views(x, vp, cam_table_, tab, n, true);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(h->s, &graph);
+        hipGraphExec_t exec = nullptr;
+        if (run.good() && ec == hipSuccess) run = net_->check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0),
+                                                             "graph instantiate");
+        else if (run.good()) run = net_->check(ec, "end capture");
+        if (graph) hipGraphDestroy(graph);
+        st = run;
+        if (st.good()) it = h->graphs.emplace(key, exec).first;
+      }
+    }
+    if (st.good()) st = net_->check(hipGraphLaunch(it->second, h->s), "graph launch");
+  } else {
+    st = net_->run_views(x, vp, cam_table_, vd.data(), n);
+  }
   if (st.good()) st = net_->check(hipLaunchHostFunc(h->s, done, ctx), "hipLaunchHostFunc");
   if (!st.good()) {
     // part of the batch may be queued: let it finish before the slot is reused

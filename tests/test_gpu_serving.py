@@ -75,6 +75,48 @@ def test_served_views_equal_alone(wfile, precision):
     served.close()
 
 
+def test_served_graph_replays_equal_eager(wfile):
+    """Served batches replayed from captured graphs (one per slot and batch
+    shape) equal the same requests served with graphs off, bit for bit, over
+    three rounds with host synchronisation and eager work in between, so
+    every shape is replayed several times."""
+    from paper_2112_10603_amd import Net
+    print("case serving graph replay", flush=True)
+    arc = scenes.camera_arc(43, 64, 96, 3, 96, (3.0, 10.0), 5.0, 0.01).to(DEV)
+    arc2 = scenes.camera_arc(44, 48, 80, 2, 64, (3.0, 8.0), 4.0, 0.01).to(DEV)
+    nets = {g: Net(wfile, "bf16", 0, hbm_budget_bytes=8 << 30, tick_ms=2.0, max_batch_views=4, graphs=g)
+            for g in (True, False)}
+    for net in nets.values():
+        for i in range(3):
+            net.register_camera(i, arc[i].contiguous())
+        for i in range(2):
+            net.register_camera(10 + i, arc2[i].contiguous())
+    rng = np.random.default_rng(11)
+    reqs = []
+    for k in range(14):
+        if k % 3 == 2:
+            reqs.append(((10, 11), float(rng.uniform(0, 1)), (3, 48, 80)))
+        else:
+            j = int(rng.integers(0, 2))
+            reqs.append(((j, j + 1), float(rng.uniform(0, 1)), (3, 64, 96)))
+    outs = {}
+    for g, net in nets.items():
+        outs[g] = []
+        for rnd in range(3):
+            o = [torch.full(shape, -1.0, device=DEV) for _, _, shape in reqs]
+            tickets = [net.submit(p[0], p[1], t, oo) for (p, t, _), oo in zip(reqs, o)]
+            _wait(net, tickets)
+            torch.cuda.synchronize()
+            torch.zeros(1 << 20, device=DEV).add_(1.0)  # eager work between rounds
+            outs[g].append(o)
+    for rnd in range(3):
+        for k in range(len(reqs)):
+            assert torch.equal(outs[True][rnd][k], outs[False][rnd][k]), (rnd, k)
+            assert torch.equal(outs[True][rnd][k], outs[True][0][k]), (rnd, k)
+    for net in nets.values():
+        net.close()
+
+
 def test_serving_errors(wfile):
     from paper_2112_10603_amd import FfvError, Net
     net = Net(wfile, "bf16", 0, hbm_budget_bytes=4 << 30)
