@@ -192,11 +192,14 @@ ffv_status ffv_calibrate(ffv_net* net, const ffv_pair* pair, float t);
  * camera's padded image, its image pyramid and its context features
  * resident in device memory, and every request reuses them. Requests are
  * admitted in FIFO order once per tick (opts.tick_ms) or when a running
- * batch finishes, grouped per resolution into batches of at most
- * opts.max_batch_views, while the bytes of resident cameras plus the
- * workspaces of batches in flight stay within opts.hbm_budget_bytes. Each
- * batch runs on its own stream, so batches overlap on the device. A view's
- * result does not depend on the batch it runs in.
+ * batch finishes, into batches of at most opts.max_batch_views that span
+ * at most four camera sizes (a request of a fifth size waits for a later
+ * batch), while the bytes of resident cameras plus the workspaces of
+ * batches in flight stay within opts.hbm_budget_bytes. A batch's workspace
+ * is sized for its largest height and width, and every layer of a batch is
+ * one launch over all its views whatever their sizes. Each batch runs on
+ * its own stream, so batches overlap on the device. A view's result does
+ * not depend on the batch it runs in.
  */
 
 /* Copy a DEVICE planar [3][H][W] float32 image in [0,1] as camera cam_id
@@ -227,6 +230,14 @@ typedef struct {
  * out), FFV_ERR_BUDGET (one view can never fit the budget), FFV_ERR_STATE
  * (serving off, or an FP8 net not yet calibrated). */
 ffv_status ffv_submit(ffv_net* net, const ffv_request* req, uint64_t* ticket);
+
+/* Queue n requests (HOST array) at once, tickets[i] for reqs[i] (HOST
+ * array of n): every request is checked as in ffv_submit before any is
+ * queued, so on an error none is (ffv_last_error names the first bad
+ * index). The scheduler sees them together, so a burst lands in as few
+ * batches as max_batch_views and the four-size limit allow. n = 0 is a
+ * no-op. Thread-safe. */
+ffv_status ffv_submit_many(ffv_net* net, const ffv_request* reqs, int32_t n, uint64_t* tickets);
 
 /* FFV_PENDING while queued or running; FFV_OK once the output is written
  * (fills *timing if non-NULL; the ticket is then collected). If the

@@ -4,6 +4,7 @@
 #include <exception>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/ffv.h"
 #include "fault.h"
@@ -237,6 +238,28 @@ ffv_status ffv_submit(ffv_net* net, const ffv_request* req, uint64_t* ticket) {
   r.tag = req->user_tag;
   try {
     return from(net->net.server()->submit(r, ticket));
+  } catch (const std::exception& e) {
+    return fail(FFV_ERR_DEVICE, e.what());
+  }
+}
+
+ffv_status ffv_submit_many(ffv_net* net, const ffv_request* reqs, int32_t n, uint64_t* tickets) {
+  if (!net || n < 0 || (n > 0 && (!reqs || !tickets))) return fail(FFV_ERR_ARG, "null argument");
+  if (!net->net.server()) return fail(FFV_ERR_STATE, "serving is off (hbm_budget_bytes = 0)");
+  if (!net->net.ready()) return fail(FFV_ERR_STATE, "FP8 net needs ffv_calibrate first");
+  std::vector<ffv::Request> rs(n);
+  for (int i = 0; i < n; ++i) {
+    rs[i].cam_l = reqs[i].cam_left;
+    rs[i].cam_r = reqs[i].cam_right;
+    rs[i].t = reqs[i].t;
+    rs[i].out = reqs[i].out;
+    rs[i].tag = reqs[i].user_tag;
+  }
+  try {
+    int bad = -1;
+    const ffv::Status st = net->net.server()->submit_many(rs.data(), n, tickets, &bad);
+    if (!st.good() && bad >= 0) return fail(st.code, "request " + std::to_string(bad) + ": " + st.msg);
+    return from(st);
   } catch (const std::exception& e) {
     return fail(FFV_ERR_DEVICE, e.what());
   }

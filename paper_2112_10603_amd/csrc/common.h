@@ -62,6 +62,18 @@ struct ConvArgs {
   const void* zero;     // >= 16 bytes of zeros (read for taps outside the image)
 };
 
+// One launch of the implicit-GEMM kernel over up to kMax groups of images
+// of different sizes (views of several resolutions in one batch): group g
+// owns the workgroups first[g] .. first[g+1]-1 along grid x and runs with
+// a[g]; the groups share the layer (weights, channels, mode), so grid y and
+// z are common.
+struct ConvGroup {
+  static constexpr int kMax = 4;
+  ConvArgs a[kMax];
+  int n;
+  int first[kMax + 1];
+};
+
 // N-tile widths the conv kernel is instantiated for (the M tile is 256);
 // H32: the halo-reuse kernel (16x16 output pixels x 32 channels, stride-1
 // 3x3 neighbourhoods only; the M-tile width must be 16); H256, H128: the
@@ -100,6 +112,15 @@ bool conv_resident_ok(DType dt, const ConvArgs& a, int bn);
 bool conv_resident_s2_ok(DType dt, const ConvArgs& a, int bn);
 
 hipError_t launch_conv(DType dt, ConvTile tile, const ConvArgs& a, hipStream_t s);
+// One launch over n (1 .. ConvGroup::kMax) groups of images of the same
+// layer; with more than one group only the generic tiles (N*) and the
+// two-group halo tile (P256) run it.
+hipError_t launch_conv_grouped(DType dt, ConvTile tile, const ConvArgs* a, int n, hipStream_t s);
+// Whether a tile can run a launch of several groups.
+inline bool conv_tile_groupable(ConvTile t) {
+  return t == ConvTile::N256 || t == ConvTile::N128 || t == ConvTile::N64 || t == ConvTile::N32 ||
+         t == ConvTile::P256;
+}
 // Width of the 2-D pixel block of a 256-pixel M tile for a Ho x Wo grid:
 // the least padded area, the squarest block on ties.
 int conv_tile_width(int Ho, int Wo);
@@ -117,13 +138,17 @@ struct CamDev {
 };
 
 // Per-view description: the two cameras (indices into the CamDev table),
-// the phase and where the view's planar [3][H][W] output goes.
+// the phase, where the view's planar [3][H][W] output goes, and the view's
+// own size: real (h, w) and padded to multiples of 16 (hp, wp). A launch
+// over views of several sizes is sized for the largest: per-view buffers
+// are strided by the launch's size, each view's data laid out with its own
+// width at the start of its slot, and threads past a view's own size exit.
 struct ViewDesc {
   int cam_l, cam_r;
   float t;
-  int pad;
+  int hp;
   float* out;
-  void* pad2;
+  int wp, h, w, pad;
 };
 
 hipError_t launch_ingest(const float* const* src, int n_cam, int H, int W, int Hp, int Wp,
@@ -137,8 +162,10 @@ hipError_t launch_transition(const ViewDesc* views, int n_views, const CamDev* c
                              float* FM, DType dt, int t_plane, hipStream_t s);
 hipError_t launch_final(const ViewDesc* views, int n_views, const CamDev* cams, const float* FM,
                         int h, int w, float* I2, void* x0u, int ld, DType dt, hipStream_t s);
-hipError_t launch_flow_down(const float* in, int in_ld, int n_img, int h, int w, float* out,
-                            hipStream_t s);
+// Flow pyramid level k+1 from level k (k = 0: full resolution) of every
+// view: in/out strided by the launch's level sizes h x w and h/2 x w/2.
+hipError_t launch_flow_down(const float* in, int in_ld, const ViewDesc* views, int n_img, int k, int h, int w,
+                            float* out, hipStream_t s);
 hipError_t launch_ctx_warp(const ViewDesc* views, int n_views, const CamDev* cams, int level, int C,
                            const float* flow, int h, int w, void* dst, int dst_ld,
                            long dst_img_stride, DType dt, hipStream_t s);

@@ -39,37 +39,39 @@ hipError_t launch_s2(const ConvArgs& a, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_t(ConvTile tile, const ConvArgs& a, hipStream_t s) {
+hipError_t launch_t(ConvTile tile, const ConvArgs* g, int n, hipStream_t s) {
   using namespace convk;
+  // the persistent kernels take one image group
+  if (!conv_tile_groupable(tile) && n != 1) return hipErrorInvalidValue;
   switch (tile) {
     case ConvTile::N256:
-      return launch_variant<T, 256, 256, 4, 2, 128, 2, 1>(a, s);
+      return launch_variant<T, 256, 256, 4, 2, 128, 2, 1>(g, n, s);
     case ConvTile::N128:
-      return launch_variant<T, 256, 128, 4, 2, 128, 2, 1>(a, s);
+      return launch_variant<T, 256, 128, 4, 2, 128, 2, 1>(g, n, s);
     case ConvTile::N64:
-      return launch_variant<T, 256, 64, 8, 1, 128, 2, 1>(a, s);
+      return launch_variant<T, 256, 64, 8, 1, 128, 2, 1>(g, n, s);
     case ConvTile::N32:
-      return launch_variant<T, 256, 32, 8, 1, 128, 2, 1>(a, s);
+      return launch_variant<T, 256, 32, 8, 1, 128, 2, 1>(g, n, s);
     case ConvTile::H32:
-      return launch_halo<T>(a, s);
+      return launch_halo<T>(g[0], s);
     case ConvTile::H256:
-      return launch_variant<T, 256, 256, 4, 2, 128, 2, 1, true>(a, s);
+      return launch_variant<T, 256, 256, 4, 2, 128, 2, 1, true>(g, n, s);
     case ConvTile::H128:
-      return launch_variant<T, 256, 128, 4, 2, 128, 2, 1, true>(a, s);
+      return launch_variant<T, 256, 128, 4, 2, 128, 2, 1, true>(g, n, s);
     case ConvTile::Q256:
-      return launch_variant<T, 256, 256, 2, 4, 128, 2, 1, true>(a, s);
+      return launch_variant<T, 256, 256, 2, 4, 128, 2, 1, true>(g, n, s);
     case ConvTile::P256:
-      return launch_variant<T, 256, 256, 4, 2, 128, 2, 1, true, true>(a, s);
+      return launch_variant<T, 256, 256, 4, 2, 128, 2, 1, true, true>(g, n, s);
     case ConvTile::R32:
-      return launch_resident<T, 32>(a, s);
+      return launch_resident<T, 32>(g[0], s);
     case ConvTile::R64:
-      return launch_resident<T, 64>(a, s);
+      return launch_resident<T, 64>(g[0], s);
     case ConvTile::S32:
-      return launch_s2<T, 32>(a, s);
+      return launch_s2<T, 32>(g[0], s);
     case ConvTile::S64:
-      return launch_s2<T, 64>(a, s);
+      return launch_s2<T, 64>(g[0], s);
     case ConvTile::S128:
-      return launch_s2<T, 128>(a, s);
+      return launch_s2<T, 128>(g[0], s);
   }
   return hipErrorInvalidValue;
 }
@@ -114,11 +116,21 @@ int conv_tile_width(int Ho, int Wo) {
   return best;
 }
 
+hipError_t launch_conv_grouped(DType dt, ConvTile tile, const ConvArgs* g, int n, hipStream_t s) {
+  if (n < 1 || n > ConvGroup::kMax) return hipErrorInvalidValue;
+  // groups with no work are left out
+  ConvArgs live[ConvGroup::kMax];
+  int m = 0;
+  for (int i = 0; i < n; ++i)
+    if (g[i].n_img > 0 && g[i].Ho > 0 && g[i].Wo > 0) live[m++] = g[i];
+  if (m == 0) return hipSuccess;
+  if (dt == DType::F32) return launch_t<float>(tile, live, m, s);
+  if (dt == DType::FP8) return launch_t<f8>(tile, live, m, s);
+  return launch_t<bf16>(tile, live, m, s);
+}
+
 hipError_t launch_conv(DType dt, ConvTile tile, const ConvArgs& a, hipStream_t s) {
-  if (a.n_img <= 0 || a.Ho <= 0 || a.Wo <= 0) return hipSuccess;
-  if (dt == DType::F32) return launch_t<float>(tile, a, s);
-  if (dt == DType::FP8) return launch_t<f8>(tile, a, s);
-  return launch_t<bf16>(tile, a, s);
+  return launch_conv_grouped(dt, tile, &a, 1, s);
 }
 
 }  // namespace ffv

@@ -194,9 +194,18 @@ constexpr int kHaloRows = 340;
 __host__ __device__ constexpr bool halo_width_ok(int tw) { return tw == 8 || tw == 16 || tw == 32; }
 
 template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES, int SWZ, bool SW, bool HALO,
-          bool PP = false>
-__global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
+          bool PP = false, bool GRP = false>
+__global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvGroup ga) {
   using C = Conv<T, BM, BN, WM, WN, KB, STAGES, SWZ>;
+  // GRP: several image groups; this workgroup's group (uniform) gives its
+  // arguments and its range of grid x. Without GRP the arguments sit at a
+  // fixed kernarg offset, so their loads need not wait for a lookup.
+  int grp = 0;
+  if constexpr (GRP) {
+    for (int g = 1; g < ga.n; ++g)
+      if ((int)blockIdx.x >= ga.first[g]) grp = g;
+  }
+  const ConvArgs a = ga.a[grp];  // a copy: its fields stay in registers
   static_assert(!HALO || (BM == 256 && STAGES == 2), "halo tiles: 256 pixels, two stages");
   static_assert(!PP || (HALO && BN == 256 && WM * WN == 8 && C::CH == 8),
                 "two-group schedule: 256x256 halo tiles of eight waves, 128-byte steps");
@@ -237,8 +246,8 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvArgs a) {
 
   // XCD-aware M-tile order: consecutive workgroup ids go round-robin over
   // the 8 XCDs; give each XCD a contiguous range of tiles.
-  const int gx = gridDim.x;
-  const int bx = blockIdx.x;
+  const int gx = GRP ? ga.first[grp + 1] - ga.first[grp] : (int)gridDim.x;
+  const int bx = GRP ? (int)blockIdx.x - ga.first[grp] : (int)blockIdx.x;
   const int xcd = bx & 7, q = gx >> 3, r = gx & 7;
   const int mt = xcd * q + min(xcd, r) + (bx >> 3);
 
@@ -824,37 +833,72 @@ inline bool halo_tile_ok(const ConvArgs& a, int bk) {
 
 template <typename T, int BM, int BN, int WM, int WN, int KB, int STAGES, int SWZ = 0, bool HALO = false,
           bool PP = false>
-hipError_t launch_variant(const ConvArgs& a, hipStream_t s) {
+hipError_t launch_variant(const ConvArgs* args, int n_groups, hipStream_t s) {
   using C = Conv<T, BM, BN, WM, WN, KB, STAGES, SWZ>;
-  if (HALO && !halo_tile_ok(a, C::BK)) return hipErrorInvalidValue;
+  if (n_groups < 1 || n_groups > ConvGroup::kMax) return hipErrorInvalidValue;
+  ConvGroup ga{};
+  ga.n = n_groups;
+  long total = 0;
+  const ConvArgs& a0 = args[0];
   // phase-grouped 256-column HALO tiles: WN phases per workgroup
-  const bool paired = HALO && BN == 256 && (WN == 2 || WN == 4) && a.transposed == 1;
-  if (paired && (a.n_rows > BN / WN || a.cout_pad < BN / WN)) return hipErrorInvalidValue;
-  const int phases = a.transposed == 1 ? (paired ? 4 / WN : 4) : 1;
-  const int n_tiles = paired ? 1 : (a.n_rows + BN - 1) / BN;
-  // every B row a tile reads (n_tiles * BN of them) must exist in the packed weights
-  if (a.K_pad % C::BK != 0 || a.cin_pad % C::VEC != 0 || a.n_rows <= 0 ||
-      n_tiles * BN > a.cout_pad || a.in_ld % C::VEC != 0 || a.tile_w <= 0 || BM % a.tile_w != 0)
-    return hipErrorInvalidValue;
-  const long tiles = (long)a.n_img * ((a.Ho + BM / a.tile_w - 1) / (BM / a.tile_w)) *
-                     ((a.Wo + a.tile_w - 1) / a.tile_w);
-  if (tiles > 0x7fffffffL) return hipErrorInvalidValue;
-  // per-image input offsets are 32-bit in the kernel
-  if ((long)a.Hi * a.Wi * a.in_ld >= (1L << 31)) return hipErrorInvalidValue;
-  dim3 grid((unsigned)tiles, (unsigned)n_tiles, phases);
+  const bool paired = HALO && BN == 256 && (WN == 2 || WN == 4) && a0.transposed == 1;
+  for (int g = 0; g < n_groups; ++g) {
+    const ConvArgs& a = args[g];
+    if (HALO && !halo_tile_ok(a, C::BK)) return hipErrorInvalidValue;
+    if (paired && (a.n_rows > BN / WN || a.cout_pad < BN / WN)) return hipErrorInvalidValue;
+    const int n_tiles = paired ? 1 : (a.n_rows + BN - 1) / BN;
+    // every B row a tile reads (n_tiles * BN of them) must exist in the packed weights
+    if (a.K_pad % C::BK != 0 || a.cin_pad % C::VEC != 0 || a.n_rows <= 0 ||
+        n_tiles * BN > a.cout_pad || a.in_ld % C::VEC != 0 || a.tile_w <= 0 || BM % a.tile_w != 0)
+      return hipErrorInvalidValue;
+    // the groups share the layer: channels, mode and output layout
+    if (a.transposed != a0.transposed || a.n_rows != a0.n_rows || a.cout != a0.cout || a.taps != a0.taps ||
+        a.out_f32 != a0.out_f32 || a.out_ld != a0.out_ld || (a.out_scale == nullptr) != (a0.out_scale == nullptr))
+      return hipErrorInvalidValue;
+    // per-image input offsets are 32-bit in the kernel
+    if ((long)a.Hi * a.Wi * a.in_ld >= (1L << 31)) return hipErrorInvalidValue;
+    const long tiles = (long)a.n_img * ((a.Ho + BM / a.tile_w - 1) / (BM / a.tile_w)) *
+                       ((a.Wo + a.tile_w - 1) / a.tile_w);
+    ga.a[g] = a;
+    ga.first[g] = (int)total;
+    total += tiles;
+    if (total > 0x7fffffffL) return hipErrorInvalidValue;
+  }
+  ga.first[n_groups] = (int)total;
+  if (total == 0) return hipSuccess;
+  const int phases = a0.transposed == 1 ? (paired ? 4 / WN : 4) : 1;
+  const int n_tiles = paired ? 1 : (a0.n_rows + BN - 1) / BN;
+  dim3 grid((unsigned)total, (unsigned)n_tiles, phases);
   // the staged epilogue needs bf16/fp8 outputs in 16-byte channel runs
-  const int run = a.out_scale ? 16 : 8;
-  const bool staged = sizeof(T) != 4 && BN >= 128 && a.transposed != 2 && !a.out_f32 &&
-                      a.cout % run == 0 && a.out_ld % run == 0;
+  const int run = a0.out_scale ? 16 : 8;
+  const bool staged = sizeof(T) != 4 && BN >= 128 && a0.transposed != 2 && !a0.out_f32 &&
+                      a0.cout % run == 0 && a0.out_ld % run == 0;
+  if (n_groups > 1) {
+    // grouped launches: the generic tiles and the two-group halo tile
+    if constexpr (!HALO || PP) {
+      if constexpr (sizeof(T) != 4 && BN >= 128) {
+        if (staged) {
+          hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES, SWZ, true, HALO, PP, true>), grid,
+                             dim3(C::NT), 0, s, ga);
+          return hipGetLastError();
+        }
+      }
+      hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES, SWZ, false, HALO, PP, true>), grid,
+                         dim3(C::NT), 0, s, ga);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   if constexpr (sizeof(T) != 4 && BN >= 128) {
     if (staged) {
       hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES, SWZ, true, HALO, PP>), grid, dim3(C::NT),
-                         0, s, a);
+                         0, s, ga);
       return hipGetLastError();
     }
   }
   hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES, SWZ, false, HALO, PP>), grid, dim3(C::NT), 0,
-                     s, a);
+                     s, ga);
   return hipGetLastError();
 }
 

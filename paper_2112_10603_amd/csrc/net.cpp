@@ -685,6 +685,65 @@ Status Net::conv(const Exec& x, const Layer& L, const void* in, int in_ld, long 
                                      L.stride == 1)
                                         ? "conv256"
                                         : "conv");
+  if (x.n_groups > 1) {
+    // views of several sizes: one launch over the size groups, each group's
+    // images at its own size (a shift of the plan's size: every level is the
+    // padded size over a power of two) and at its offset in the buffers
+    int k = 0;
+    while (k < 8 && (x.plan_hp >> k) > Hi) ++k;
+    if ((x.plan_hp >> k) != Hi) return Status::err(-4, "grouped conv: level size");
+    int n_total = 0;
+    for (int j = 0; j < x.n_groups; ++j) n_total += x.groups[j].n;
+    if (n_total != n_img || x.n_groups > ConvGroup::kMax) return Status::err(-4, "grouped conv: groups");
+    // tiles without a grouped form (the persistent kernels, the one-group
+    // halo tiles): the generic tile of the same N width
+    ConvTile gt = tile;
+    if (!conv_tile_groupable(gt)) {
+      const int bn = conv_tile_bn(gt);
+      gt = bn == 32 ? ConvTile::N32 : (bn == 64 ? ConvTile::N64 : (bn == 128 ? ConvTile::N128 : ConvTile::N256));
+    }
+    bool halo_tile = gt == ConvTile::P256;
+    const size_t in_e = in_fp8 ? 1 : dtype_size(dt_);
+    const size_t out_e = out_f32 ? 4 : (out_fp8 ? 1 : dtype_size(dt_));
+    ConvArgs g[ConvGroup::kMax];
+    double gflops = 0.0;
+    for (int j = 0; j < x.n_groups; ++j) {
+      const ViewGroup& vg = x.groups[j];
+      ConvArgs& b = g[j];
+      b = a;
+      b.n_img = vg.n;
+      b.Hi = vg.Hp >> k;
+      b.Wi = vg.Wp >> k;
+      if (L.transposed) {
+        b.Ho = b.Hi;
+        b.Wo = b.Wi;
+        b.Hout = 2 * b.Hi;
+        b.Wout = 2 * b.Wi;
+      } else {
+        b.Ho = (b.Hi - 1) / L.stride + 1;
+        b.Wo = (b.Wi - 1) / L.stride + 1;
+        b.Hout = b.Ho;
+        b.Wout = b.Wo;
+      }
+      b.in = static_cast<const char*>(in) + (size_t)vg.first * in_img_stride * in_e;
+      b.out = static_cast<char*>(out) + (size_t)vg.first * out_img_stride * out_e;
+      b.tile_w = halo_tile ? halo_default_width(kdt, b) : conv_tile_width(b.Ho, b.Wo);
+      if (b.tile_w == 0) {
+        // the halo tiles cannot take this group: the generic tile of the same
+        // N width for every group (restart; the generic tile takes any width)
+        gt = conv_tile_bn(gt) == 256 ? ConvTile::N256 : ConvTile::N128;
+        halo_tile = false;
+        j = -1;
+        gflops = 0.0;
+        continue;
+      }
+      gflops += 2.0 * vg.n * (double)b.Hout * b.Wout * L.cout * L.cin * (L.transposed ? 4.0 : 9.0);
+    }
+    prof_begin(x);
+    Status st = check(launch_conv_grouped(kdt, gt, g, x.n_groups, x.s), L.name.c_str());
+    prof_end(x, cls, gflops);
+    return st;
+  }
   prof_begin(x);
   Status st = check(launch_conv(kdt, tile, a, x.s), L.name.c_str());
   prof_end(x, cls, flops);
@@ -832,7 +891,7 @@ Status Net::run_views(const Exec& x, const ViewPlan& p, const CamDev* cams,
       const int ho = h / 2, wo = w / 2;
       const long Pk = (long)ho * wo;
       prof_begin(x);
-      FFV_TRY(check(launch_flow_down(src, ld, nv, h, w, (float*)x.at(p.Fp[k]), x.s), "flow_down"));
+      FFV_TRY(check(launch_flow_down(src, ld, views, nv, k, h, w, (float*)x.at(p.Fp[k]), x.s), "flow_down"));
       FFV_TRY(check(launch_ctx_warp(views, nv, cams, k, cw[k], (const float*)x.at(p.Fp[k]), ho, wo,
                                     x.at(p.lvl[k]) + lv_off[k] * e, lv_ld[k], Pk * lv_ld[k], dt_, x.s),
                     "ctx_warp"));
@@ -1010,6 +1069,10 @@ Status Net::run_call(const float* const* left, const float* const* right, int n_
       d.cam_r = ri[i];
       d.t = t[j];
       d.out = outs[(size_t)i * n_t + j];
+      d.hp = g.Hp;
+      d.wp = g.Wp;
+      d.h = g.H;
+      d.w = g.W;
     }
   // Graph replay needs every per-call value in device tables: the camera
   // and image tables above, and here all views' descriptors.

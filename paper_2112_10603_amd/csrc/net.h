@@ -70,12 +70,23 @@ struct Geo {
   bool operator==(const Geo& o) const { return H == o.H && W == o.W; }
 };
 
-// Where kernels run: a stream and the base of a workspace.
+// Views of one size in a batch of several sizes: views first .. first+n-1,
+// padded full-resolution size Hp x Wp.
+struct ViewGroup {
+  int first = 0, n = 0, Hp = 0, Wp = 0;
+};
+
+// Where kernels run: a stream and the base of a workspace; for a batch of
+// views of several sizes, its size groups (the plan is sized for the
+// largest, plan_hp being its padded height).
 struct Exec {
   hipStream_t s = nullptr;
   char* ws = nullptr;
   bool prof = false;
   bool capture = false;  // the stream is being captured into a graph
+  const ViewGroup* groups = nullptr;
+  int n_groups = 0;
+  int plan_hp = 0;
   char* at(size_t off) const { return ws + off; }
 };
 

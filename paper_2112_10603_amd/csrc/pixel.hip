@@ -172,10 +172,10 @@ template <typename T>
 __global__ void assemble0_k(const ViewDesc* views, const CamDev* cams, int h, int w, T* x, int ld,
                             int t_plane) {
   const int v = blockIdx.y;
-  const long P = (long)h * w;
+  const long P = (long)h * w;  // slot stride
   const long p = (long)blockIdx.x * TPB + threadIdx.x;
-  if (p >= P) return;
   const ViewDesc d = views[v];
+  if (p >= (long)(d.hp >> 2) * (d.wp >> 2)) return;
   const float4 l = ld4(cams[d.cam_l].L0 + 4 * p);
   const float4 r = ld4(cams[d.cam_r].L0 + 4 * p);
   const float vals[8] = {l.x, l.y, l.z, r.x, r.y, r.z, t_plane ? d.t : 0.f, 0.f};
@@ -189,20 +189,22 @@ __global__ void transition_k(const ViewDesc* views, const CamDev* cams, int leve
                              const float* FMprev, int hp, int wp, int h, int w, T* x, int ld,
                              float* FM, int t_plane) {
   const int v = blockIdx.y;
-  const long P = (long)h * w;
+  const long P = (long)h * w;  // slot strides: P here, hp * wp for the previous level
   const long p = (long)blockIdx.x * TPB + threadIdx.x;
-  if (p >= P) return;
   const ViewDesc d = views[v];
-  const int y = (int)(p / w), xx = (int)(p % w);
+  const int vh = d.hp >> (2 - level), vw = d.wp >> (2 - level);  // this view's level sizes
+  const int vhp = vh >> 1, vwp = vw >> 1;
+  if (p >= (long)vh * vw) return;
+  const int y = (int)(p / vw), xx = (int)(p % vw);
   int y0, y1, x0, x1;
   float by, ax;
-  hp_tap(y, hp, h, y0, y1, by);
-  hp_tap(xx, wp, w, x0, x1, ax);
+  hp_tap(y, vhp, vh, y0, y1, by);
+  hp_tap(xx, vwp, vw, x0, x1, ax);
   const float* fp = FMprev + (long)v * hp * wp * 8;
-  const float* q00 = fp + 8L * (y0 * wp + x0);
-  const float* q01 = fp + 8L * (y0 * wp + x1);
-  const float* q10 = fp + 8L * (y1 * wp + x0);
-  const float* q11 = fp + 8L * (y1 * wp + x1);
+  const float* q00 = fp + 8L * (y0 * vwp + x0);
+  const float* q01 = fp + 8L * (y0 * vwp + x1);
+  const float* q10 = fp + 8L * (y1 * vwp + x0);
+  const float* q11 = fp + 8L * (y1 * vwp + x1);
   float up[5];
 #pragma unroll
   for (int c = 0; c < 5; ++c)
@@ -212,8 +214,8 @@ __global__ void transition_k(const ViewDesc* views, const CamDev* cams, int leve
   const float* Lc = level == 1 ? cams[d.cam_l].L1 : cams[d.cam_l].X4;
   const float* Rc = level == 1 ? cams[d.cam_r].L1 : cams[d.cam_r].X4;
   const float4 L = ld4(Lc + 4 * p), R = ld4(Rc + 4 * p);
-  const float4 Wl = sample4(Lc, warp_taps(xx, y, Fx, Fy, w, h));
-  const float4 Wr = sample4(Rc, warp_taps(xx, y, Gx, Gy, w, h));
+  const float4 Wl = sample4(Lc, warp_taps(xx, y, Fx, Fy, vw, vh));
+  const float4 Wr = sample4(Rc, warp_taps(xx, y, Gx, Gy, vw, vh));
 
   const float vals[24] = {L.x, L.y, L.z, R.x, R.y, R.z, Wl.x, Wl.y, Wl.z, Wr.x, Wr.y, Wr.z,
                           Mt, Fx, Fy, Gx, Gy, t_plane ? d.t : 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -230,19 +232,20 @@ __global__ void final_k(const ViewDesc* views, const CamDev* cams, const float* 
   long bx;
   int v;
   view_fastest_order(bx, v);
-  const long P = (long)h * w;
+  const long P = (long)h * w;  // slot stride
   const long p = bx * TPB + threadIdx.x;
-  if (p >= P) return;
   const ViewDesc d = views[v];
-  const int y = (int)(p / w), xx = (int)(p % w);
+  const int vh = d.hp, vw = d.wp;  // this view's size
+  if (p >= (long)vh * vw) return;
+  const int y = (int)(p / vw), xx = (int)(p % vw);
   const float* f = FM + ((long)v * P + p) * 8;
   const float4 F = ld4(f);
   const float M = f[4];
   const float* Lc = cams[d.cam_l].X4;
   const float* Rc = cams[d.cam_r].X4;
   const float4 L = ld4(Lc + 4 * p), R = ld4(Rc + 4 * p);
-  const float4 Wl = sample4(Lc, warp_taps(xx, y, F.x, F.y, w, h));
-  const float4 Wr = sample4(Rc, warp_taps(xx, y, F.z, F.w, w, h));
+  const float4 Wl = sample4(Lc, warp_taps(xx, y, F.x, F.y, vw, vh));
+  const float4 Wr = sample4(Rc, warp_taps(xx, y, F.z, F.w, vw, vh));
   const float m = 1.f / (1.f + expf(-M));
   float4 o;
   o.x = m * Wl.x + (1.f - m) * Wr.x;
@@ -260,28 +263,32 @@ __global__ void final_k(const ViewDesc* views, const CamDev* cams, const float* 
 __global__ void blend_out_k(const float* I2, const ViewDesc* views, int Hp, int Wp, int H, int W) {
   const int v = blockIdx.y;
   const long p = (long)blockIdx.x * TPB + threadIdx.x;
-  if (p >= (long)H * W) return;
-  const int y = (int)(p / W), x = (int)(p % W);
-  const float4 b = ld4(I2 + ((long)v * Hp * Wp + (long)y * Wp + x) * 4);
-  const long HW = (long)H * W;
-  float* o = views[v].out;
+  const ViewDesc d = views[v];
+  if (p >= (long)d.h * d.w) return;
+  const int y = (int)(p / d.w), x = (int)(p % d.w);
+  const float4 b = ld4(I2 + ((long)v * Hp * Wp + (long)y * d.wp + x) * 4);
+  const long HW = (long)d.h * d.w;
+  float* o = d.out;
   o[p] = b.x;
   o[HW + p] = b.y;
   o[2 * HW + p] = b.z;
 }
 
 // -------------------------------------------- flow pyramid: F/2 of 2x2 mean
-__global__ void flow_down_k(const float* in, int in_ld, int h, int w, float* out) {
+__global__ void flow_down_k(const float* in, int in_ld, const ViewDesc* views, int k, int h, int w, float* out) {
   const int img = blockIdx.y;
-  const int ho = h / 2, wo = w / 2;
+  const int ho = h / 2, wo = w / 2;  // slot strides: h x w in, ho x wo out
   const long p = (long)blockIdx.x * TPB + threadIdx.x;
-  if (p >= (long)ho * wo) return;
-  const int y = (int)(p / wo), x = (int)(p % wo);
+  const ViewDesc d = views[img];
+  const int vw = d.wp >> k;  // this view's level-k width
+  const int vwo = vw >> 1;
+  if (p >= (long)((d.hp >> k) >> 1) * vwo) return;
+  const int y = (int)(p / vwo), x = (int)(p % vwo);
   const float* b = in + (long)img * h * w * in_ld;
-  const float4 a = ld4(b + (long)in_ld * ((2 * y) * w + 2 * x));
-  const float4 c = ld4(b + (long)in_ld * ((2 * y) * w + 2 * x + 1));
-  const float4 e = ld4(b + (long)in_ld * ((2 * y + 1) * w + 2 * x));
-  const float4 g = ld4(b + (long)in_ld * ((2 * y + 1) * w + 2 * x + 1));
+  const float4 a = ld4(b + (long)in_ld * ((2 * y) * vw + 2 * x));
+  const float4 c = ld4(b + (long)in_ld * ((2 * y) * vw + 2 * x + 1));
+  const float4 e = ld4(b + (long)in_ld * ((2 * y + 1) * vw + 2 * x));
+  const float4 g = ld4(b + (long)in_ld * ((2 * y + 1) * vw + 2 * x + 1));
   float4 r;
   r.x = 0.5f * (0.5f * (0.5f * (a.x + c.x) + 0.5f * (e.x + g.x)));
   r.y = 0.5f * (0.5f * (0.5f * (a.y + c.y) + 0.5f * (e.y + g.y)));
@@ -298,17 +305,18 @@ __global__ void ctx_warp_k(const ViewDesc* views, const CamDev* cams, int level,
                            const float* flow, int h, int w, T* dst, int dst_ld, long dst_img_stride) {
   const int v = blockIdx.y;
   const int G = C / 4;  // groups for both sides
-  const long P = (long)h * w;
+  const long P = (long)h * w;  // slot stride
   const long id = (long)blockIdx.x * TPB + threadIdx.x;
-  if (id >= P * G) return;
+  const ViewDesc d = views[v];
+  const int vh = d.hp >> (level + 1), vw = d.wp >> (level + 1);  // this view's level size
+  if (id >= (long)vh * vw * G) return;
   const long p = id / G;
   const int g = (int)(id - p * G);
   const bool right = g >= G / 2;
   const int c0 = (right ? g - G / 2 : g) * 8;
-  const ViewDesc d = views[v];
-  const int y = (int)(p / w), x = (int)(p % w);
+  const int y = (int)(p / vw), x = (int)(p % vw);
   const float4 F = ld4(flow + ((long)v * P + p) * 4);
-  const Tap4 t = right ? warp_taps(x, y, F.z, F.w, w, h) : warp_taps(x, y, F.x, F.y, w, h);
+  const Tap4 t = right ? warp_taps(x, y, F.z, F.w, vw, vh) : warp_taps(x, y, F.x, F.y, vw, vh);
   const T* src = reinterpret_cast<const T*>(cams[right ? d.cam_r : d.cam_l].ctx[level]) + c0;
   float acc[8];
 #pragma unroll
@@ -368,9 +376,16 @@ __global__ void head_k(const T* u4, int ld, const float* wgt, const float* bias,
   __syncthreads();
   const int v = blockIdx.y;
   const long p = (long)blockIdx.x * TPB + threadIdx.x;
-  if (p >= (long)H * W) return;
+  const ViewDesc d = views[v];
+  if (p >= (long)d.h * d.w) return;
+  const long slot = (long)v * Hp * Wp;  // slot stride of the launch's size
+  // this view's size from here on
+  H = d.h;
+  W = d.w;
+  Hp = d.hp;
+  Wp = d.wp;
   const int y = (int)(p / W), x = (int)(p % W);
-  const T* base = u4 + (long)v * Hp * Wp * ld;
+  const T* base = u4 + slot * ld;
   float z0 = bias[0], z1 = bias[1], z2 = bias[2];
 #pragma unroll
   for (int tap = 0; tap < 9; ++tap) {
@@ -390,10 +405,10 @@ __global__ void head_k(const T* u4, int ld, const float* wgt, const float* bias,
       }
     }
   }
-  const float4 b = ld4(I2 + ((long)v * Hp * Wp + (long)y * Wp + x) * 4);
+  const float4 b = ld4(I2 + (slot + (long)y * Wp + x) * 4);
   const float r0 = 1.f / (1.f + expf(-z0)), r1 = 1.f / (1.f + expf(-z1)), r2 = 1.f / (1.f + expf(-z2));
   const long HW = (long)H * W;
-  float* o = views[v].out;
+  float* o = d.out;
   o[p] = fminf(fmaxf(b.x + 2.f * r0 - 1.f, 0.f), 1.f);
   o[HW + p] = fminf(fmaxf(b.y + 2.f * r1 - 1.f, 0.f), 1.f);
   o[2 * HW + p] = fminf(fmaxf(b.z + 2.f * r2 - 1.f, 0.f), 1.f);
@@ -429,10 +444,17 @@ __global__ __launch_bounds__(TPB) void head_mfma_k(const bf16* u4, int ld, const
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lrow = lane & 31, lhalf = lane >> 5;
   const int v = blockIdx.y;
+  const ViewDesc d = views[v];
+  const long slot = (long)v * Hp * Wp;  // slot stride of the launch's size
+  // this view's size from here on
+  H = d.h;
+  W = d.w;
+  Hp = d.hp;
+  Wp = d.wp;
   const long HW = (long)H * W;
-  const bf16* base = u4 + (long)v * Hp * Wp * ld + 8 * lhalf;
+  const bf16* base = u4 + slot * ld + 8 * lhalf;
   const float bias0 = bias[0], bias1 = bias[1], bias2 = bias[2];
-  float* o = views[v].out;
+  float* o = d.out;
   // Two groups per iteration: every load of both (the taps and the blend
   // input) is issued before their MFMAs, so each pair waits for one memory
   // round trip instead of four.
@@ -459,7 +481,7 @@ __global__ __launch_bounds__(TPB) void head_mfma_k(const bf16* u4, int ld, const
         for (int j = 0; j < NC; ++j)
           av[u][tap][j] = ok ? *reinterpret_cast<const uint4*>(src + 16 * j) : make_uint4(0u, 0u, 0u, 0u);
       }
-      b[u] = ld4(I2 + ((long)v * Hp * Wp + (long)y[u] * Wp + x[u]) * 4);
+      b[u] = ld4(I2 + (slot + (long)y[u] * Wp + x[u]) * 4);
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
@@ -575,10 +597,10 @@ hipError_t launch_final(const ViewDesc* views, int n_views, const CamDev* cams, 
   return hipGetLastError();
 }
 
-hipError_t launch_flow_down(const float* in, int in_ld, int n_img, int h, int w, float* out,
-                            hipStream_t s) {
+hipError_t launch_flow_down(const float* in, int in_ld, const ViewDesc* views, int n_img, int k, int h, int w,
+                            float* out, hipStream_t s) {
   if (n_img <= 0) return hipSuccess;
-  hipLaunchKernelGGL(flow_down_k, grid1((long)(h / 2) * (w / 2), n_img), dim3(TPB), 0, s, in, in_ld,
+  hipLaunchKernelGGL(flow_down_k, grid1((long)(h / 2) * (w / 2), n_img), dim3(TPB), 0, s, in, in_ld, views, k,
                      h, w, out);
   return hipGetLastError();
 }

@@ -4,6 +4,8 @@
 // device waits on.
 #include "scheduler.h"
 
+#include <algorithm>
+
 #include <chrono>
 
 namespace ffv {
@@ -123,17 +125,21 @@ Status Scheduler::register_camera(int id, const float* image, int H, int W) {
   return Status::ok();
 }
 
-Status Scheduler::submit(const Request& r, uint64_t* ticket) {
+Status Scheduler::check_locked(const Request& r, int* H, int* W) const {
   if (!r.out) return Status::err(kErrArg, "null output pointer");
   if (!(r.t >= 0.f && r.t <= 1.f)) return Status::err(kErrArg, "t must lie in [0, 1]");
-  std::lock_guard<std::mutex> lk(mu_);
   auto a = cams_.find(r.cam_l), b = cams_.find(r.cam_r);
   if (a == cams_.end() || b == cams_.end()) return Status::err(kErrArg, "unknown camera id");
   if (a->second.H != b->second.H || a->second.W != b->second.W)
     return Status::err(kErrArg, "cameras of a pair differ in size");
-  const int H = a->second.H, W = a->second.W;
-  if (resident_bytes_ + ex_->batch_bytes(H, W, 1) > budget_)
+  *H = a->second.H;
+  *W = a->second.W;
+  if (resident_bytes_ + ex_->batch_bytes(*H, *W, 1) > budget_)
     return Status::err(kErrBudget, "request can never fit the HBM budget");
+  return Status::ok();
+}
+
+uint64_t Scheduler::enqueue_locked(const Request& r, int H, int W) {
   const uint64_t id = next_ticket_++;
   Ticket& t = tickets_[id];
   t.req = r;
@@ -142,8 +148,32 @@ Status Scheduler::submit(const Request& r, uint64_t* ticket) {
   t.tm.t_submit = now_seconds();
   t.state.store(0, std::memory_order_relaxed);
   queue_.push_back(id);
-  *ticket = id;
+  return id;
+}
+
+Status Scheduler::submit(const Request& r, uint64_t* ticket) {
+  std::lock_guard<std::mutex> lk(mu_);
+  int H = 0, W = 0;
+  const Status st = check_locked(r, &H, &W);
+  if (!st.good()) return st;
   // admitted at the next tick or when a running batch completes
+  *ticket = enqueue_locked(r, H, W);
+  return Status::ok();
+}
+
+Status Scheduler::submit_many(const Request* rs, int n, uint64_t* tickets, int* bad) {
+  if (bad) *bad = -1;
+  if (n < 0 || (n > 0 && (!rs || !tickets))) return Status::err(kErrArg, "bad request array");
+  std::lock_guard<std::mutex> lk(mu_);
+  std::vector<std::pair<int, int>> hw(n);
+  for (int i = 0; i < n; ++i) {
+    const Status st = check_locked(rs[i], &hw[i].first, &hw[i].second);
+    if (!st.good()) {
+      if (bad) *bad = i;
+      return st;
+    }
+  }
+  for (int i = 0; i < n; ++i) tickets[i] = enqueue_locked(rs[i], hw[i].first, hw[i].second);
   return Status::ok();
 }
 
@@ -203,20 +233,35 @@ void Scheduler::fail_tickets(const std::vector<Ticket*>& tks, const Status& st) 
 
 void Scheduler::admit_and_launch() {
   while (!queue_.empty() && paused_ == 0) {
-    const Ticket& head = tickets_[queue_.front()];
-    const int H = head.H, W = head.W;
-    // FIFO within one resolution
+    // FIFO over the queue, at most kMaxSizes resolutions in a batch
     std::vector<size_t> pick;
+    std::vector<std::pair<int, int>> sizes;
     for (size_t i = 0; i < queue_.size() && (int)pick.size() < max_batch_; ++i) {
       const Ticket& t = tickets_[queue_[i]];
-      if (t.H == H && t.W == W) pick.push_back(i);
+      const std::pair<int, int> hw(t.H, t.W);
+      if (std::find(sizes.begin(), sizes.end(), hw) == sizes.end()) {
+        if ((int)sizes.size() == kMaxSizes) continue;
+        sizes.push_back(hw);
+      }
+      pick.push_back(i);
     }
     int n = (int)pick.size();
+    // the largest height and width among the first m picks
+    auto max_size = [&](int m, int* H, int* W) {
+      *H = *W = 0;
+      for (int i = 0; i < m; ++i) {
+        const Ticket& t = tickets_[queue_[pick[i]]];
+        *H = std::max(*H, t.H);
+        *W = std::max(*W, t.W);
+      }
+    };
+    int H = 0, W = 0;
     // a free slot large enough, or room in the budget for one
     Slot* slot = nullptr;
     int slot_idx = -1;
     Status alloc_err;
     while (n >= 1 && !slot) {
+      max_size(n, &H, &W);
       const size_t need = ex_->batch_bytes(H, W, n);
       for (size_t i = 0; i < slots_.size(); ++i)
         if (!slots_[i]->busy.load(std::memory_order_acquire) && slots_[i]->bytes >= need) {
@@ -287,6 +332,8 @@ void Scheduler::admit_and_launch() {
       j.cam_r = cams_[t.req.cam_r].index;
       j.t = t.req.t;
       j.out = t.req.out;
+      j.H = t.H;
+      j.W = t.W;
     }
     for (int i = n - 1; i >= 0; --i) queue_.erase(queue_.begin() + pick[i]);
     slot->tickets = tks;

@@ -10,8 +10,10 @@
 // per view):
 //   - requests are queued in submission order and admitted once per tick,
 //     or as soon as a running batch completes;
-//   - a batch holds queued requests of the head request's resolution, in
-//     FIFO order, at most max_batch of them;
+//   - a batch holds the queued requests in FIFO order, at most max_batch of
+//     them and of at most kMaxSizes distinct resolutions (a request of one
+//     more resolution waits for a later batch); the device runs every layer
+//     of a batch as one launch over its resolution groups;
 //   - a batch runs on a slot (a stream with its own workspace); a free slot
 //     that is large enough is reused, else one is grown or created while
 //     resident cameras plus all slot workspaces stay within the budget; a
@@ -45,11 +47,12 @@ struct Timing {
   double t_submit = 0, t_admit = 0, t_launch = 0, t_done = 0;
 };
 
-// One view of a batch: camera table indices, phase, output.
+// One view of a batch: camera table indices, phase, output, and its size.
 struct ViewJob {
   int cam_l = 0, cam_r = 0;
   float t = 0.f;
   float* out = nullptr;
+  int H = 0, W = 0;
 };
 
 // Device side of the scheduler. Every call but launch()'s completion
@@ -57,7 +60,8 @@ struct ViewJob {
 class Executor {
  public:
   virtual ~Executor() = default;
-  // Device bytes of one resident camera and of one batch workspace.
+  // Device bytes of one resident camera, and of the workspace of a batch of
+  // n views whose largest height and width are H and W.
   virtual size_t camera_bytes(int H, int W) const = 0;
   virtual size_t batch_bytes(int H, int W, int n) const = 0;
   // Copy `image` (device, planar [3][H][W]) and build its resident data as
@@ -72,7 +76,8 @@ class Executor {
   virtual void slot_destroy(void* slot) = 0;
   // Block until the work queued on the slot is done.
   virtual void slot_wait(void* slot) = 0;
-  // Queue a batch of n views of size H x W on the slot. On success, done(ctx)
+  // Queue a batch of n views (each of its own size; H x W the largest
+  // height and width among them) on the slot. On success, done(ctx)
   // runs exactly once, on any thread and without blocking, after the
   // outputs are written. On failure nothing of the batch is left running
   // and done is not called.
@@ -83,6 +88,7 @@ class Executor {
 class Scheduler {
  public:
   static constexpr int kMaxCams = 1024;
+  static constexpr int kMaxSizes = 4;  // resolutions per batch
   Scheduler(Executor* ex, size_t budget, float tick_ms, int max_batch);
   // Stops admitting, waits for the batches in flight, frees slots and
   // cameras. Tickets never admitted are dropped.
@@ -92,6 +98,10 @@ class Scheduler {
   // the batches in flight are done).
   Status register_camera(int id, const float* image, int H, int W);
   Status submit(const Request& r, uint64_t* ticket);
+  // Queue n requests at once: all are checked first and none is queued if
+  // one fails (its index in *bad when non-null); the queue takes them in
+  // order under one lock, so one admission sees all of them.
+  Status submit_many(const Request* rs, int n, uint64_t* tickets, int* bad);
   // *done = false while queued or running. Once finished the ticket is
   // collected: *done = true with the timing, or the status of a failed batch.
   Status poll(uint64_t ticket, Timing* timing, bool* done);
@@ -106,6 +116,8 @@ class Scheduler {
   void resume();
 
  private:
+  Status check_locked(const Request& r, int* H, int* W) const;
+  uint64_t enqueue_locked(const Request& r, int H, int W);
   struct Camera {
     int H = 0, W = 0;
     void* handle = nullptr;

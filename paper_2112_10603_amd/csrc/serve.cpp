@@ -3,8 +3,10 @@
 // batch of views, completed by a host function queued behind them.
 #include "serve.h"
 
+#include <algorithm>
 #include <map>
-#include <tuple>
+#include <numeric>
+#include <vector>
 
 #include "fault.h"
 
@@ -12,14 +14,15 @@ namespace ffv {
 
 namespace {
 
-// A slot's captured batches: one graph per (height, width, views), valid
-// for the slot's current workspace and the net's graph epoch.
+// A slot's captured batches: one graph per batch layout (the size groups'
+// heights, widths and view counts), valid for the slot's current workspace
+// and the net's graph epoch.
 struct HSlot {
   hipStream_t s = nullptr;
   char* ws = nullptr;
   size_t bytes = 0;
   uint64_t epoch = 0;
-  std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
+  std::map<std::vector<int>, hipGraphExec_t> graphs;
   void drop_graphs() {
     for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
     graphs.clear();
@@ -137,20 +140,54 @@ Status HipExecutor::launch(void* slot, int H, int W, const ViewJob* jobs, int n,
   HSlot* h = static_cast<HSlot*>(slot);
   if (fault_hit("launch")) return Status::err(kErrDevice, "injected launch fault (FFV_FAULT)");
   hipSetDevice(net_->device());
+  // views ordered by size (stable), one group per size; the workspace is
+  // planned for the largest height and width
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return jobs[a].H != jobs[b].H ? jobs[a].H < jobs[b].H : jobs[a].W < jobs[b].W;
+  });
+  std::vector<ViewGroup> groups;
+  std::vector<int> key;
+  for (int i = 0; i < n; ++i) {
+    const ViewJob& j = jobs[order[i]];
+    if (j.H < 2 || j.W < 2 || j.H > H || j.W > W) return Status::err(kErrArg, "view size");
+    const Geo gj = Geo::of(j.H, j.W);
+    if (groups.empty() || groups.back().Hp != gj.Hp || groups.back().Wp != gj.Wp ||
+        jobs[order[i - 1]].H != j.H || jobs[order[i - 1]].W != j.W) {
+      if ((int)groups.size() == ConvGroup::kMax) return Status::err(kErrArg, "too many view sizes in a batch");
+      groups.push_back(ViewGroup{i, 0, gj.Hp, gj.Wp});
+      key.insert(key.end(), {j.H, j.W, 0});
+    }
+    ++groups.back().n;
+    ++key.back();
+  }
   const Geo g = Geo::of(H, W);
   const ViewPlan vp = net_->view_plan(g, n);
   if (vp.total > h->bytes) return Status::err(kErrArg, "batch larger than its slot");
   std::vector<ViewDesc> vd(n);
   for (int i = 0; i < n; ++i) {
+    const ViewJob& j = jobs[order[i]];
+    const Geo gj = Geo::of(j.H, j.W);
     vd[i] = ViewDesc{};
-    vd[i].cam_l = jobs[i].cam_l;
-    vd[i].cam_r = jobs[i].cam_r;
-    vd[i].t = jobs[i].t;
-    vd[i].out = jobs[i].out;
+    vd[i].cam_l = j.cam_l;
+    vd[i].cam_r = j.cam_r;
+    vd[i].t = j.t;
+    vd[i].out = j.out;
+    vd[i].hp = gj.Hp;
+    vd[i].wp = gj.Wp;
+    vd[i].h = gj.H;
+    vd[i].w = gj.W;
   }
   Exec x;
   x.s = h->s;
   x.ws = h->ws;
+  if (groups.size() > 1) {
+    x.groups = groups.data();
+    x.n_groups = (int)groups.size();
+    x.plan_hp = g.Hp;
+  }
+  key.insert(key.begin(), {H, W});
   Status st;
   if (net_->graphs_enabled()) {
     // The batch's view descriptors go to the slot's device table first, so a
@@ -164,7 +201,6 @@ Status HipExecutor::launch(void* slot, int H, int W, const ViewJob* jobs, int n,
       h->drop_graphs();
       h->epoch = epoch;
     }
-    const auto key = std::make_tuple(H, W, n);
     auto it = h->graphs.find(key);
     if (st.good() && it == h->graphs.end()) {
       if (h->graphs.size() >= 128) h->drop_graphs();  // bound the cache (batch shapes vary)

@@ -26,7 +26,7 @@ STATUS = {0: "FFV_OK", 1: "FFV_PENDING", -1: "FFV_ERR_ARG", -2: "FFV_ERR_OOM",
 
 # Every symbol include/ffv.h declares.
 EXPORTS = ["ffv_default_opts", "ffv_create_net", "ffv_destroy_net", "ffv_interpolate",
-           "ffv_last_error", "ffv_calibrate", "ffv_register_camera", "ffv_submit", "ffv_poll", "ffv_serving_stats",
+           "ffv_last_error", "ffv_calibrate", "ffv_register_camera", "ffv_submit", "ffv_submit_many", "ffv_poll", "ffv_serving_stats",
            "ffv_debug_tap", "ffv_set_debug", "ffv_set_profiling", "ffv_kernel_stats", "ffv_op_conv",
            "ffv_autotune", "ffv_save_tuning", "ffv_load_tuning", "ffv_interpolate_blend",
            "ffv_interpolate_recursive", "ffv_stitch_cluster", "ffv_debug_fault", "ffv_op_conv_noalloc",
@@ -123,6 +123,8 @@ def lib() -> ctypes.CDLL:
     L.ffv_register_camera.restype = c_int
     L.ffv_submit.argtypes = [c_void, ctypes.POINTER(ffv_request), ctypes.POINTER(ctypes.c_uint64)]
     L.ffv_submit.restype = c_int
+    L.ffv_submit_many.argtypes = [c_void, ctypes.POINTER(ffv_request), c_int, ctypes.POINTER(ctypes.c_uint64)]
+    L.ffv_submit_many.restype = c_int
     L.ffv_poll.argtypes = [c_void, ctypes.c_uint64, ctypes.POINTER(ffv_timing)]
     L.ffv_poll.restype = c_int
     L.ffv_serving_stats.argtypes = [c_void, ctypes.POINTER(ctypes.c_int64),
@@ -282,6 +284,25 @@ class Net:
         torch.cuda.current_stream(self.device).synchronize()
         _check(lib().ffv_submit(self._h, ctypes.byref(req), ctypes.byref(tk)))
         return tk.value
+
+    def submit_many(self, reqs) -> list:
+        """Queue several views at once: ``reqs`` holds (cam_left, cam_right,
+        t, out) tuples, checked like ``submit``; none is queued if one is
+        bad. The scheduler sees the whole burst together. Returns the
+        tickets in order."""
+        reqs = list(reqs)
+        arr = (ffv_request * max(1, len(reqs)))()
+        for i, (cl, cr, t, out) in enumerate(reqs):
+            _dev_f32(out, "out")
+            hw = self._cam_shapes.get(cl)
+            if hw is not None and tuple(out.shape) != (3,) + hw:
+                raise ValueError(f"request {i}: out must be [3, {hw[0]}, {hw[1]}] for camera {cl}, got "
+                                 f"{list(out.shape)}")
+            arr[i] = ffv_request(cl, cr, float(t), out.data_ptr(), 0)
+        tks = (ctypes.c_uint64 * max(1, len(reqs)))()
+        torch.cuda.current_stream(self.device).synchronize()
+        _check(lib().ffv_submit_many(self._h, arr, len(reqs), tks))
+        return [tks[i] for i in range(len(reqs))]
 
     def poll(self, ticket: int):
         """None while pending; the timing dict once the view is written.

@@ -133,6 +133,8 @@ class FakeExecutor : public Executor {
     if (fault_hit("launch")) return Status::err(kErrDevice, "injected launch fault");
     Slot* s = static_cast<Slot*>(slot);
     if (batch_bytes(H, W, n) > s->bytes) return Status::err(kErrArg, "batch larger than slot");
+    for (int i = 0; i < n; ++i)
+      if (jobs[i].H > H || jobs[i].W > W) return Status::err(kErrArg, "view larger than the batch");
     Batch b{H, W, std::vector<ViewJob>(jobs, jobs + n)};
     std::vector<int> ids(n * 2);
     {
@@ -151,7 +153,7 @@ class FakeExecutor : public Executor {
     s->q.push_back([this, b, ids, delay, done, ctx] {
       std::this_thread::sleep_for(std::chrono::milliseconds(delay));
       for (size_t i = 0; i < b.jobs.size(); ++i)
-        for (int k = 0; k < 3 * b.H * b.W; ++k)
+        for (int k = 0; k < 3 * b.jobs[i].H * b.jobs[i].W; ++k)
           b.jobs[i].out[k] = view_value(ids[2 * i], ids[2 * i + 1], b.jobs[i].t);
       {
         std::lock_guard<std::mutex> g(mu_);
@@ -303,8 +305,8 @@ static void test_fifo_one_batch() {
   std::printf("ok fifo_one_batch\n");
 }
 
-// More requests than max_batch: batches of max_batch in FIFO order; a
-// batch holds one resolution (the head request's).
+// More requests than max_batch: batches of max_batch in FIFO order; sizes
+// mix within a batch, whose slot geometry is its largest view's.
 static void test_split_and_resolution() {
   FakeExecutor ex(kBig, 2);
   {
@@ -318,7 +320,6 @@ static void test_split_and_resolution() {
     std::vector<Out> small(10, Out(4, 4)), large(3, Out(8, 8));
     std::vector<uint64_t> tks;
     s.pause();
-    // order: S0 L0 S1 S2 S3 S4 L1 S5 S6 S7 S8 S9 L2
     int si = 0, li = 0;
     const char* order = "SLSSSSLSSSSSL";
     for (const char* o = order; *o; ++o) {
@@ -328,21 +329,65 @@ static void test_split_and_resolution() {
     s.resume();
     for (uint64_t tk : tks) CHECK(wait_ticket(s, tk) == 0);
     auto bs = ex.batches();
-    // S0..S3 | L0 L1 L2 | S4..S7 | S8 S9
+    // S0 L0 S1 S2 | S3 S4 L1 S5 | S6..S9 | L2
     CHECK(bs.size() == 4);
     if (bs.size() == 4) {
-      CHECK(bs[0].H == 4 && bs[0].jobs.size() == 4 && bs[0].jobs[0].out == small[0].p() &&
-            bs[0].jobs[3].out == small[3].p());
-      CHECK(bs[1].H == 8 && bs[1].jobs.size() == 3 && bs[1].jobs[0].out == large[0].p() &&
-            bs[1].jobs[2].out == large[2].p());
-      CHECK(bs[2].H == 4 && bs[2].jobs.size() == 4 && bs[2].jobs[0].out == small[4].p());
-      CHECK(bs[3].H == 4 && bs[3].jobs.size() == 2 && bs[3].jobs[1].out == small[9].p());
+      CHECK(bs[0].H == 8 && bs[0].W == 8 && bs[0].jobs.size() == 4);
+      CHECK(bs[0].jobs[0].out == small[0].p() && bs[0].jobs[0].H == 4 && bs[0].jobs[0].W == 4);
+      CHECK(bs[0].jobs[1].out == large[0].p() && bs[0].jobs[1].H == 8 && bs[0].jobs[1].W == 8);
+      CHECK(bs[0].jobs[3].out == small[2].p());
+      CHECK(bs[1].H == 8 && bs[1].jobs.size() == 4 && bs[1].jobs[2].out == large[1].p() &&
+            bs[1].jobs[3].out == small[5].p());
+      CHECK(bs[2].H == 4 && bs[2].W == 4 && bs[2].jobs.size() == 4 &&
+            bs[2].jobs[0].out == small[6].p() && bs[2].jobs[3].out == small[9].p());
+      CHECK(bs[3].H == 8 && bs[3].jobs.size() == 1 && bs[3].jobs[0].out == large[2].p());
     }
-    for (auto& o : small) CHECK(o.px[0] == view_value(1, 2, 0.5f));
-    for (auto& o : large) CHECK(o.px[0] == view_value(3, 4, 0.5f));
+    for (auto& o : small) {
+      CHECK(o.px[0] == view_value(1, 2, 0.5f));
+      CHECK(o.px[3 * 4 * 4 - 1] == view_value(1, 2, 0.5f));
+    }
+    for (auto& o : large) CHECK(o.px[3 * 8 * 8 - 1] == view_value(3, 4, 0.5f));
   }
   CHECK(ex.live_allocs() == 0);
   std::printf("ok split_and_resolution\n");
+}
+
+// A batch spans at most four sizes: a request of a fifth size waits for the
+// next batch while later requests of the four sizes join this one; the slot
+// geometry is the largest height and the largest width, which may come from
+// different views.
+static void test_size_limit_per_batch() {
+  FakeExecutor ex(kBig, 2);
+  {
+    Scheduler s(&ex, kBig, 5.f, 8);
+    CHECK(s.start().good());
+    const int hs[5] = {4, 6, 8, 4, 10}, ws[5] = {8, 6, 4, 4, 2};
+    std::vector<Image> cams;
+    for (int k = 0; k < 5; ++k) cams.emplace_back(k + 1, hs[k], ws[k]);
+    for (int k = 0; k < 5; ++k) CHECK(s.register_camera(k, cams[k].px.data(), hs[k], ws[k]).good());
+    std::vector<Out> outs;
+    const int seq[7] = {0, 1, 2, 3, 4, 0, 2};
+    for (int k : seq) outs.emplace_back(hs[k], ws[k]);
+    std::vector<uint64_t> tks;
+    s.pause();
+    for (int i = 0; i < 7; ++i) tks.push_back(submit(s, seq[i], seq[i], 0.25f, outs[i].p()));
+    s.resume();
+    for (uint64_t tk : tks) CHECK(wait_ticket(s, tk) == 0);
+    auto bs = ex.batches();
+    CHECK(bs.size() == 2);
+    if (bs.size() == 2) {
+      CHECK(bs[0].jobs.size() == 6 && bs[0].H == 8 && bs[0].W == 8);
+      const int want[6] = {0, 1, 2, 3, 5, 6};
+      for (int i = 0; i < 6 && i < (int)bs[0].jobs.size(); ++i) CHECK(bs[0].jobs[i].out == outs[want[i]].p());
+      CHECK(bs[1].jobs.size() == 1 && bs[1].H == 10 && bs[1].W == 2 && bs[1].jobs[0].out == outs[4].p());
+    }
+    for (int i = 0; i < 7; ++i) {
+      const int k = seq[i];
+      CHECK(outs[i].px[3 * hs[k] * ws[k] - 1] == view_value(k + 1, k + 1, 0.25f));
+    }
+  }
+  CHECK(ex.live_allocs() == 0);
+  std::printf("ok size_limit_per_batch\n");
 }
 
 // A budget that holds the cameras and one 2-view workspace: batches are
@@ -551,6 +596,54 @@ static void test_arguments() {
   std::printf("ok arguments\n");
 }
 
+// submit_many: a bad request queues none of them (its index reported); a
+// good burst of two sizes is admitted as one batch, in order.
+static void test_submit_many() {
+  FakeExecutor ex(kBig, 1);
+  {
+    Scheduler s(&ex, kBig, 2.f, 8);
+    CHECK(s.start().good());
+    Image a(1, 4, 4), b(2, 4, 4), c(3, 6, 10), d(4, 6, 10);
+    CHECK(s.register_camera(0, a.px.data(), 4, 4).good());
+    CHECK(s.register_camera(1, b.px.data(), 4, 4).good());
+    CHECK(s.register_camera(2, c.px.data(), 6, 10).good());
+    CHECK(s.register_camera(3, d.px.data(), 6, 10).good());
+    std::vector<Out> outs;
+    for (int i = 0; i < 6; ++i) outs.emplace_back(i % 3 == 1 ? 6 : 4, i % 3 == 1 ? 10 : 4);
+    std::vector<Request> rs(6);
+    for (int i = 0; i < 6; ++i) {
+      rs[i].cam_l = i % 3 == 1 ? 2 : 0;
+      rs[i].cam_r = i % 3 == 1 ? 3 : 1;
+      rs[i].t = 0.125f * i;
+      rs[i].out = outs[i].p();
+    }
+    uint64_t tks[6] = {};
+    int bad = -1;
+    rs[3].cam_r = 9;  // unknown camera
+    CHECK(s.submit_many(rs.data(), 6, tks, &bad).code == kErrArg && bad == 3);
+    rs[3].cam_r = 1;
+    long adm = 0, comp = 0, queued = 0;
+    size_t bytes = 0;
+    CHECK(s.stats(&adm, &comp, &queued, &bytes).good() && queued == 0 && adm == 0);
+    CHECK(s.submit_many(rs.data(), 0, nullptr, &bad).good());
+    CHECK(s.submit_many(rs.data(), 6, tks, &bad).good() && bad == -1);
+    for (uint64_t tk : tks) CHECK(wait_ticket(s, tk) == 0);
+    auto bs = ex.batches();
+    CHECK(bs.size() == 1);
+    if (bs.size() == 1) {
+      CHECK(bs[0].H == 6 && bs[0].W == 10 && bs[0].jobs.size() == 6);
+      for (int i = 0; i < 6 && i < (int)bs[0].jobs.size(); ++i) CHECK(bs[0].jobs[i].out == outs[i].p());
+    }
+    for (int i = 0; i < 6; ++i) {
+      const bool big = i % 3 == 1;
+      CHECK(outs[i].px[big ? 3 * 6 * 10 - 1 : 3 * 4 * 4 - 1] ==
+            view_value(big ? 3 : 1, big ? 4 : 2, 0.125f * i));
+    }
+  }
+  CHECK(ex.live_allocs() == 0);
+  std::printf("ok submit_many\n");
+}
+
 // Several submitting threads at once (ThreadSanitizer's main case): every
 // request completes with its own value.
 static void test_threads() {
@@ -593,6 +686,8 @@ int main(int argc, char** argv) {
     void (*fn)();
   } tests[] = {{"fifo_one_batch", test_fifo_one_batch},
                {"split_and_resolution", test_split_and_resolution},
+               {"size_limit_per_batch", test_size_limit_per_batch},
+               {"submit_many", test_submit_many},
                {"budget_admission", test_budget_admission},
                {"slot_reuse_and_overlap", test_slot_reuse_and_overlap},
                {"launch_fault", test_launch_fault},

@@ -1,6 +1,7 @@
 """Serving through the C ABI: resident cameras, queued requests, continuous
-batching across resolutions; every served view equals the same view computed
-alone by ffv_interpolate, bit for bit."""
+batching with several camera sizes in one batch (one launch per layer);
+every served view equals the same view computed alone by ffv_interpolate,
+bit for bit."""
 import time
 
 import numpy as np
@@ -115,6 +116,58 @@ def test_served_graph_replays_equal_eager(wfile):
             assert torch.equal(outs[True][rnd][k], outs[True][0][k]), (rnd, k)
     for net in nets.values():
         net.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_mixed_size_batch_one_launch(wfile, precision):
+    """Eight requests of four camera sizes (even, ragged, one taller and one
+    wider than the rest, so the slot's height and width come from different
+    views) queued at once run as ONE batch (one launch time), twice (the
+    second replays the batch's graph); every view equals the view computed
+    alone, bit for bit."""
+    from paper_2112_10603_amd import Net
+    print(f"case serving mixed-size batch {precision}", flush=True)
+    sizes = [(64, 96), (37, 53), (72, 40), (48, 80)]
+    served = Net(wfile, precision, 0, hbm_budget_bytes=8 << 30, tick_ms=2.0, max_batch_views=8)
+    alone = Net(wfile, precision, 0)
+    cams = {}
+    for k, (h, w) in enumerate(sizes):
+        arc = scenes.camera_arc(50 + k, h, w, 2, max(h, w), (3.0, 9.0), 4.0, 0.01).to(DEV)
+        for i in range(2):
+            cams[10 * k + i] = arc[i].contiguous()
+            served.register_camera(10 * k + i, cams[10 * k + i])
+    rng = np.random.default_rng(9)
+    order = [0, 1, 2, 3, 3, 2, 1, 0]
+    reqs = [(10 * k, 10 * k + 1, float(rng.uniform(0, 1))) for k in order]
+    refs = [alone.interpolate([(cams[l], cams[r])], [t])[0, 0] for l, r, t in reqs]
+    for rnd in range(2):
+        outs = [torch.full((3,) + sizes[k], -1.0, device=DEV) for k in order]
+        tickets = served.submit_many([(l, r, t, o) for (l, r, t), o in zip(reqs, outs)])
+        done = _wait(served, tickets)
+        launches = {done[tk]["t_launch"] for tk in tickets}
+        assert len(launches) == 1, (rnd, sorted(launches))
+        torch.cuda.synchronize()
+        for k, (o, ref) in enumerate(zip(outs, refs)):
+            assert torch.equal(o, ref), (rnd, k, reqs[k], (o - ref).abs().max().item())
+    alone.close()
+    served.close()
+
+
+def test_submit_many_all_or_nothing(wfile):
+    from paper_2112_10603_amd import FfvError, Net
+    net = Net(wfile, "bf16", 0, hbm_budget_bytes=4 << 30)
+    img = torch.rand(3, 32, 32, device=DEV)
+    net.register_camera(0, img)
+    net.register_camera(1, img)
+    outs = [torch.empty(3, 32, 32, device=DEV) for _ in range(3)]
+    with pytest.raises(FfvError) as e:
+        net.submit_many([(0, 1, 0.5, outs[0]), (0, 7, 0.5, outs[1]), (0, 1, 0.2, outs[2])])
+    assert e.value.code == -1 and "request 1" in str(e.value)
+    assert net.serving_stats()["queued"] == 0 and net.serving_stats()["admitted"] == 0
+    assert net.submit_many([]) == []
+    tks = net.submit_many([(0, 1, 0.5, outs[0]), (1, 0, 0.2, outs[1])])
+    _wait(net, tks)
+    net.close()
 
 
 def test_serving_errors(wfile):

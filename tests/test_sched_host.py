@@ -1,7 +1,7 @@
 """Host-only tests of the serving scheduler behind a fake executor (no GPU).
 
 ``tests/native/sched_test.cpp`` drives ``csrc/scheduler.cpp`` (admission under
-the budget, FIFO and per-resolution batching, slot reuse, overlapping
+the budget, FIFO batching of mixed sizes, slot reuse, overlapping
 batches, launch and allocation fault injection with status codes and no
 leak, many submitting threads). It is built three ways: plain, under
 AddressSanitizer + UndefinedBehaviorSanitizer (g++) and under
