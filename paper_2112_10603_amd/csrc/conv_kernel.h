@@ -48,6 +48,8 @@
 // full 256-column step's work without extra MFMAs.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace ffv {
@@ -801,21 +803,50 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvGroup ga) {
         }
       }
       __syncthreads();  // the region is read back by other lanes of the wave
-      for (int q = lane; q < TM * cpr; q += 64) {
-        const int p = q / cpr, ch = q - p * cpr;
-        const int row = wm * TM + p;
-        int oy = ty0 + row / TW;
-        int ox = tx0 + row % TW;
-        const int n = col0 + ch * (16 / E);
-        if (oy >= a.Ho || ox >= a.Wo || n >= a.cout) continue;
-        if (a.transposed) {
-          oy *= 2;
-          ox *= 2;
+      // Read-back: lane l takes chunk l % CPR of wave-tile rows l / CPR +
+      // R * it (R = 64 / CPR rows per step). Every chunk is read from LDS
+      // first, then stored; the output position advances by R rows per step
+      // without a division.
+      auto flush = [&](auto cpr_c) {
+        constexpr int CPR = decltype(cpr_c)::value;
+        constexpr int R = 64 / CPR, IT = TM / R;
+        const int ch = lane % CPR, p_l = lane / CPR;
+        uint4 w[IT];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+          const int p = p_l + R * it;
+          w[it] = *reinterpret_cast<const uint4*>(region + p * (CPR * 16) + ((ch ^ (p & (CPR - 1))) * 16));
         }
-        const long off = (long)img_t * a.out_img_stride + ((long)(oy + py) * a.Wout + ox + px) * a.out_ld + n;
-        const uint4 w = *reinterpret_cast<const uint4*>(region + p * pitch + ((ch ^ (p & (cpr - 1))) * 16));
-        *reinterpret_cast<uint4*>(reinterpret_cast<char*>(a.out) + off * E) = w;
-      }
+        // every read is issued before the first store waits for them
+#pragma unroll
+        for (int it = 0; it < IT; ++it) asm volatile("" ::"v"(w[it].x), "v"(w[it].y), "v"(w[it].z), "v"(w[it].w));
+        const int n = col0 + ch * (16 / E);
+        if (n >= a.cout) return;
+        const int row0 = wm * TM + p_l;
+        int ry = row0 / TW, rx = row0 - ry * TW;  // row within the M tile's TH x TW block
+        const int dy = R / TW, dx = R - dy * TW;  // R rows further (uniform)
+        char* out = reinterpret_cast<char*>(a.out);
+        const long img_off = (long)img_t * a.out_img_stride + n;
+        const int sh = a.transposed ? 1 : 0;
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+          const int oy = ty0 + ry, ox = tx0 + rx;
+          if (oy < a.Ho && ox < a.Wo) {
+            const int q = ((oy << sh) + py) * a.Wout + (ox << sh) + px;  // output pixel
+            *reinterpret_cast<uint4*>(out + (img_off + (long)q * a.out_ld) * E) = w[it];
+          }
+          rx += dx;
+          ry += dy;
+          if (rx >= TW) {
+            rx -= TW;
+            ++ry;
+          }
+        }
+      };
+      if (E == 2)
+        flush(std::integral_constant<int, TN * 2 / 16>{});
+      else
+        flush(std::integral_constant<int, TN / 16>{});
     }
   }
 }
