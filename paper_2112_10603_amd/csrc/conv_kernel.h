@@ -225,10 +225,12 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvGroup ga) {
   // an A buffer holds BM rows, or a slice's halo in the HALO variant
   constexpr int AROWS = HALO ? kHaloRows : BM;
   constexpr int RING_VECS = STAGES * (AROWS + BN) * CH;
-  // epilogue: the staged output tile (SW), then 3 x BN per-channel floats
-  constexpr int PRM_OFF_VECS = SW ? BM * BN * 2 / 16 : 0;
-  constexpr int EPI_VECS = PRM_OFF_VECS + 3 * BN * 4 / 16;
-  constexpr int SMEM_VECS = EPI_VECS > RING_VECS ? EPI_VECS : RING_VECS;
+  // epilogue: the staged output tile (SW) over the rings,
+  // and the 3 x BN per-channel floats past both (written before the rings
+  // are released)
+  constexpr int STG_VECS = SW ? BM * BN * 2 / 16 : 0;
+  constexpr int PRM_OFF_VECS = STG_VECS > RING_VECS ? STG_VECS : RING_VECS;
+  constexpr int SMEM_VECS = PRM_OFF_VECS + 3 * BN * 4 / 16;
   __shared__ __attribute__((aligned(16))) uint4 smem[SMEM_VECS];
   uint4 (*As)[AROWS * CH] = reinterpret_cast<uint4 (*)[AROWS * CH]>(smem);
   uint4 (*Bs)[BN * CH] = reinterpret_cast<uint4 (*)[BN * CH]>(smem + STAGES * AROWS * CH);
@@ -262,6 +264,21 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvGroup ga) {
   const int n0 = blockIdx.y * BN;
   // output channel of this wave's first column (paired: within its phase)
   const int col0 = paired ? 0 : n0 + wn * TN;
+  // The tile's per-channel parameters (bias, weight scale, fp8 output
+  // scale) of channels pbase .. pbase + BN - 1, one channel per thread:
+  // loaded now, so the loads complete under the main loop, and put in LDS
+  // after it.
+  static_assert(NT >= BN, "one parameter channel per thread");
+  const int pbase = (merged || paired) ? 0 : n0;
+  float pv[3] = {0.f, 1.f, 1.f};
+  if (tid < BN) {
+    const int n = pbase + tid;
+    if (n < a.cout) {
+      pv[0] = a.bias[n];
+      if (a.w_scale) pv[1] = a.w_scale[n];
+      if (a.out_scale) pv[2] = a.out_scale[n];
+    }
+  }
   const int chunk = tid % CH;  // this thread's chunk within a row
 
   const T* in = reinterpret_cast<const T*>(a.in);
@@ -677,19 +694,14 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvGroup ga) {
     }
   }
 
-  // Per-channel parameters of the tile's output channels pbase .. pbase+BN-1
-  // (bias, weight scale, fp8 output scale) staged once in LDS once every
-  // wave is done with the rings: one global load per thread and one wait,
-  // instead of a dependent global load per channel group in every lane.
-  const int pbase = (merged || paired) ? 0 : n0;
+  // The per-channel parameters go to their own LDS area (outside the rings
+  // and the staging area); the barrier that releases the rings makes them
+  // visible to every wave.
   float* prm = reinterpret_cast<float*>(smem + PRM_OFF_VECS);
-  __syncthreads();
-  for (int c = tid; c < BN; c += NT) {
-    const int n = pbase + c;
-    const bool ok = n < a.cout;
-    prm[c] = ok ? a.bias[n] : 0.f;
-    prm[BN + c] = ok && a.w_scale ? a.w_scale[n] : 1.f;
-    prm[2 * BN + c] = ok && a.out_scale ? a.out_scale[n] : 1.f;
+  if (tid < BN) {
+    prm[tid] = pv[0];
+    prm[BN + tid] = pv[1];
+    prm[2 * BN + tid] = pv[2];
   }
   __syncthreads();
 
