@@ -52,6 +52,9 @@
 
 #include "common.h"
 
+typedef __attribute__((ext_vector_type(2))) float float2v;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+
 namespace ffv {
 namespace convk {
 
@@ -764,55 +767,84 @@ __global__ __launch_bounds__(64 * WM * WN) void conv_igemm(ConvGroup ga) {
     // per group of lanes.
     const int E = a.out_scale ? 1 : 2;  // output element bytes (fp8 or bf16)
     {
-      const int pitch = TN * E;         // bytes per pixel row of the wave tile
-      const int cpr = pitch / 16;       // 16-byte chunks per row (a power of two)
       char* region = reinterpret_cast<char*>(smem) + (size_t)wave * TM * TN * 2;
-      // channel-group major, so only one group's bias and scale are live
+      // Channel-group major, so only one group's bias and scale are live.
+      // A wave64 VALU instruction takes four cycles, so this loop (128
+      // values per lane) is specialised on the uniform flags: ReLU, output
+      // type and (calibration only) the running |max|, with no per-value
+      // branch; bf16 pairs convert with one instruction.
+      auto convert = [&](auto relu_c, auto e_c, auto amax_c) {
+        constexpr bool RELU = decltype(relu_c)::value, AMAX = decltype(amax_c)::value;
+        constexpr int EE = decltype(e_c)::value;
+        constexpr int PITCH = TN * EE, CPR = PITCH / 16;
 #pragma unroll
-      for (int j = 0; j < FN; ++j) {
+        for (int j = 0; j < FN; ++j) {
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          const int c0 = j * 32 + 8 * g + 4 * lhalf;  // channel within the wave tile
-          const int n = col0 + c0;
-          const bool nok = n < a.cout;  // cout is a multiple of 8: all four or none
-          const float* pc = prm + (n - pbase);  // in [0, BN), 16-byte aligned
-          const float4 bias4 = *reinterpret_cast<const float4*>(pc);
-          const float4 ws4 = *reinterpret_cast<const float4*>(pc + BN);
-          const float4 o4 = *reinterpret_cast<const float4*>(pc + 2 * BN);
-          const float bq[4] = {bias4.x, bias4.y, bias4.z, bias4.w};
-          const float sq[4] = {ws4.x, ws4.y, ws4.z, ws4.w};
-          const float os[4] = {o4.x, o4.y, o4.z, o4.w};
-#pragma unroll
-          for (int i = 0; i < FM; ++i) {
-            const int p = i * 32 + lrow;
-            float v[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              float x = acc[i][j][4 * g + q] * sq[q] + bq[q];
-              if (a.relu) x = fmaxf(x, 0.f);
-              if (a.amax && nok)
-                atomicMax(reinterpret_cast<unsigned*>(a.amax) + n + q, __float_as_uint(fabsf(x)));
-              v[q] = x;
+          for (int g = 0; g < 4; ++g) {
+            const int c0 = j * 32 + 8 * g + 4 * lhalf;  // channel within the wave tile
+            const int n = col0 + c0;
+            const float* pc = prm + (n - pbase);  // in [0, BN), 16-byte aligned
+            const float4 bias4 = *reinterpret_cast<const float4*>(pc);
+            const float4 ws4 = *reinterpret_cast<const float4*>(pc + BN);
+            const float bq[4] = {bias4.x, bias4.y, bias4.z, bias4.w};
+            const float sq[4] = {ws4.x, ws4.y, ws4.z, ws4.w};
+            float os[4] = {1.f, 1.f, 1.f, 1.f};
+            if constexpr (EE == 1) {
+              const float4 o4 = *reinterpret_cast<const float4*>(pc + 2 * BN);
+              os[0] = o4.x, os[1] = o4.y, os[2] = o4.z, os[3] = o4.w;
             }
-            const int byte = c0 * E;
-            const int chunk = (byte >> 4) ^ (p & (cpr - 1));
-            char* dst = region + p * pitch + chunk * 16 + (byte & 15);
-            if (E == 2) {
-              const bf16 b0 = (bf16)v[0], b1 = (bf16)v[1], b2 = (bf16)v[2], b3 = (bf16)v[3];
-              uint2 w;
-              w.x = (uint32_t)__builtin_bit_cast(uint16_t, b0) |
-                    ((uint32_t)__builtin_bit_cast(uint16_t, b1) << 16);
-              w.y = (uint32_t)__builtin_bit_cast(uint16_t, b2) |
-                    ((uint32_t)__builtin_bit_cast(uint16_t, b3) << 16);
-              *reinterpret_cast<uint2*>(dst) = w;
-            } else {
-              uint32_t w = 0;
 #pragma unroll
-              for (int q = 0; q < 4; ++q) w |= (uint32_t)to_f8(v[q] * os[q]) << (8 * q);
-              *reinterpret_cast<uint32_t*>(dst) = w;
+            for (int i = 0; i < FM; ++i) {
+              const int p = i * 32 + lrow;
+              float v[4];
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                float x = acc[i][j][4 * g + q] * sq[q] + bq[q];
+                if constexpr (RELU) x = fmaxf(x, 0.f);
+                v[q] = x;
+              }
+              if constexpr (AMAX) {
+                if (n < a.cout)  // cout is a multiple of 8: all four or none
+#pragma unroll
+                  for (int q = 0; q < 4; ++q)
+                    atomicMax(reinterpret_cast<unsigned*>(a.amax) + n + q, __float_as_uint(fabsf(v[q])));
+              }
+              const int byte = c0 * EE;
+              const int chunk = (byte >> 4) ^ (p & (CPR - 1));
+              char* dst = region + p * PITCH + chunk * 16 + (byte & 15);
+              if constexpr (EE == 2) {
+                uint2 w;
+                w.x = __builtin_bit_cast(uint32_t, __builtin_convertvector((float2v){v[0], v[1]}, bf16x2));
+                w.y = __builtin_bit_cast(uint32_t, __builtin_convertvector((float2v){v[2], v[3]}, bf16x2));
+                *reinterpret_cast<uint2*>(dst) = w;
+              } else {
+                uint32_t w = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) w |= (uint32_t)to_f8(v[q] * os[q]) << (8 * q);
+                *reinterpret_cast<uint32_t*>(dst) = w;
+              }
             }
           }
         }
+      };
+      using T0 = std::false_type;
+      using T1 = std::true_type;
+      using E1 = std::integral_constant<int, 1>;
+      using E2 = std::integral_constant<int, 2>;
+      if (a.amax) {
+        if (E == 2) {
+          if (a.relu) convert(T1{}, E2{}, T1{});
+          else convert(T0{}, E2{}, T1{});
+        } else {
+          if (a.relu) convert(T1{}, E1{}, T1{});
+          else convert(T0{}, E1{}, T1{});
+        }
+      } else if (E == 2) {
+        if (a.relu) convert(T1{}, E2{}, T0{});
+        else convert(T0{}, E2{}, T0{});
+      } else {
+        if (a.relu) convert(T1{}, E1{}, T0{});
+        else convert(T0{}, E1{}, T0{});
       }
       __syncthreads();  // the region is read back by other lanes of the wave
       // Read-back: lane l takes chunk l % CPR of wave-tile rows l / CPR +
