@@ -946,12 +946,12 @@ hipError_t launch_variant(const ConvArgs* args, int n_groups, hipStream_t s) {
   dim3 grid((unsigned)total, (unsigned)n_tiles, phases);
   // the staged epilogue needs bf16/fp8 outputs in 16-byte channel runs
   const int run = a0.out_scale ? 16 : 8;
-  const bool staged = sizeof(T) != 4 && BN >= 128 && a0.transposed != 2 && !a0.out_f32 &&
+  const bool staged = sizeof(T) != 4 && BN >= 32 && a0.transposed != 2 && !a0.out_f32 &&
                       a0.cout % run == 0 && a0.out_ld % run == 0;
   if (n_groups > 1) {
     // grouped launches: the generic tiles and the two-group halo tile
     if constexpr (!HALO || PP) {
-      if constexpr (sizeof(T) != 4 && BN >= 128) {
+      if constexpr (sizeof(T) != 4 && BN >= 32) {
         if (staged) {
           hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES, SWZ, true, HALO, PP, true>), grid,
                              dim3(C::NT), 0, s, ga);
@@ -965,7 +965,7 @@ hipError_t launch_variant(const ConvArgs* args, int n_groups, hipStream_t s) {
       return hipErrorInvalidValue;
     }
   }
-  if constexpr (sizeof(T) != 4 && BN >= 128) {
+  if constexpr (sizeof(T) != 4 && BN >= 32) {
     if (staged) {
       hipLaunchKernelGGL((conv_igemm<T, BM, BN, WM, WN, KB, STAGES, SWZ, true, HALO, PP>), grid, dim3(C::NT),
                          0, s, ga);
