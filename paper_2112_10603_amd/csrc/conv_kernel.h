@@ -52,8 +52,6 @@
 
 #include "common.h"
 
-typedef __attribute__((ext_vector_type(2))) float float2v;
-typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
 
 namespace ffv {
 namespace convk {

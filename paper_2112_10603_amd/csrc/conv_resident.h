@@ -20,6 +20,8 @@
 // resident copy.
 #pragma once
 
+#include <type_traits>
+
 #include "conv_halo.h"
 
 namespace ffv {
@@ -74,6 +76,8 @@ void conv_resident(ConvArgs a, int n_tiles) {
 
   __shared__ __attribute__((aligned(16))) uint4 Wl[R::W_VECS];
   __shared__ __attribute__((aligned(16))) uint4 Ah[2][A_VECS];
+  // per GEMM column: bias, weight scale, fp8 output scale
+  __shared__ __attribute__((aligned(16))) float prm[3 * BN];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -114,6 +118,18 @@ void conv_resident(ConvArgs a, int n_tiles) {
   const T* in = reinterpret_cast<const T*>(a.in);
   const T* wgt = reinterpret_cast<const T*>(a.wgt) + (long)phase * a.cout_pad * a.K_pad;
   const T* zero = reinterpret_cast<const T*>(a.zero);
+
+  // The per-column parameters, once per workgroup (the pipeline's first
+  // barrier publishes them): column n of a phase-merged conv is output
+  // channel n % cout of phase n / cout.
+  const int cout_m = merged ? a.cout : 1;
+  if (tid < BN) {
+    const bool ok = tid < a.n_rows;
+    const int o = ok ? (merged ? tid % cout_m : tid) : 0;
+    prm[tid] = ok ? a.bias[o] : 0.f;
+    prm[BN + tid] = ok && a.w_scale ? a.w_scale[o] : 1.f;
+    prm[2 * BN + tid] = ok && a.out_scale ? a.out_scale[o] : 1.f;
+  }
 
   // resident weights: slot v = (row v / rcp, chunk v % rcp); the pitch's
   // last chunk is never written or read
@@ -210,7 +226,14 @@ void conv_resident(ConvArgs a, int n_tiles) {
   };
 
   // Epilogue of block t, whose last slice was computed from halo buffer buf.
-  const int cout_m = merged ? a.cout : 1;
+  // The epilogues read the parameters through an offset the compiler cannot
+  // see (an opaque zero), so it re-reads them from LDS per block instead of
+  // holding every column's values in registers across the block loop.
+  auto params = [&]() -> const float* {
+    int z;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+    return prm + z;
+  };
   // output pixel of GEMM grid point (oy, ox) when not phase-merged
   auto out_pix = [&](int oy, int ox) {
     return TAPS == 4 ? (long)(2 * oy + pyph) * a.Wout + 2 * ox + pxph : (long)oy * a.Wout + ox;
@@ -227,48 +250,73 @@ void conv_resident(ConvArgs a, int n_tiles) {
     const int pitch = BN * E, cpr = pitch / 16;
     char* region = reinterpret_cast<char*>(&Ah[buf][0]) + wave * 32 * pitch;
     __syncthreads();
+    // specialised on the uniform flags (ReLU, output type, calibration's
+    // running |max|): no per-value branch
+    auto convert = [&](auto relu_c, auto e_c, auto amax_c) {
+      constexpr bool RELU = decltype(relu_c)::value, AMAX = decltype(amax_c)::value;
+      constexpr int EE = decltype(e_c)::value;
+      constexpr int PITCH = BN * EE, CPR = PITCH / 16;
+      char* rg = reinterpret_cast<char*>(&Ah[buf][0]) + wave * 32 * PITCH;
+      const float* pr = params();
 #pragma unroll
-    for (int f = 0; f < FN; ++f) {
+      for (int f = 0; f < FN; ++f) {
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int n = f * 32 + 8 * g + 4 * lhalf;  // first of 4 GEMM columns (one output phase)
-        const bool nok = n < a.n_rows;
-        const int o = nok ? (merged ? n % cout_m : n) : 0;
-        const float4 b4 = *reinterpret_cast<const float4*>(a.bias + o);
-        const float4 s4 = a.w_scale ? *reinterpret_cast<const float4*>(a.w_scale + o) : make_float4(1.f, 1.f, 1.f, 1.f);
-        const float bq[4] = {b4.x, b4.y, b4.z, b4.w}, sq[4] = {s4.x, s4.y, s4.z, s4.w};
-        float os[4] = {1.f, 1.f, 1.f, 1.f};
-        if (E == 1) {
-          const float4 o4 = *reinterpret_cast<const float4*>(a.out_scale + o);
-          os[0] = o4.x;
-          os[1] = o4.y;
-          os[2] = o4.z;
-          os[3] = o4.w;
-        }
-        float v[4];
+        for (int g = 0; g < 4; ++g) {
+          const int n = f * 32 + 8 * g + 4 * lhalf;  // first of 4 GEMM columns (one output phase)
+          const float4 b4 = *reinterpret_cast<const float4*>(pr + n);
+          const float4 s4 = *reinterpret_cast<const float4*>(pr + BN + n);
+          const float bq[4] = {b4.x, b4.y, b4.z, b4.w}, sq[4] = {s4.x, s4.y, s4.z, s4.w};
+          float v[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          float x = acc[f][4 * g + q] * sq[q] + bq[q];
-          if (a.relu) x = fmaxf(x, 0.f);
-          if (a.amax && nok) atomicMax(reinterpret_cast<unsigned*>(a.amax) + o + q, __float_as_uint(fabsf(x)));
-          v[q] = x;
-        }
-        const int byte = n * E;
-        char* dst = region + lrow * pitch + (((byte >> 4) ^ (lrow & (cpr - 1))) << 4) + (byte & 15);
-        if (E == 2) {
-          uint2 w;
-          w.x = (uint32_t)__builtin_bit_cast(uint16_t, (bf16)v[0]) |
-                ((uint32_t)__builtin_bit_cast(uint16_t, (bf16)v[1]) << 16);
-          w.y = (uint32_t)__builtin_bit_cast(uint16_t, (bf16)v[2]) |
-                ((uint32_t)__builtin_bit_cast(uint16_t, (bf16)v[3]) << 16);
-          *reinterpret_cast<uint2*>(dst) = w;
-        } else {
-          uint32_t w = 0;
+          for (int q = 0; q < 4; ++q) {
+            float x = acc[f][4 * g + q] * sq[q] + bq[q];
+            if constexpr (RELU) x = fmaxf(x, 0.f);
+            v[q] = x;
+          }
+          if constexpr (AMAX) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) w |= (uint32_t)to_f8(v[q] * os[q]) << (8 * q);
-          *reinterpret_cast<uint32_t*>(dst) = w;
+            for (int q = 0; q < 4; ++q)
+              if (n + q < a.n_rows) {
+                const int o = merged ? (n + q) % cout_m : n + q;
+                atomicMax(reinterpret_cast<unsigned*>(a.amax) + o, __float_as_uint(fabsf(v[q])));
+              }
+          }
+          const int byte = n * EE;
+          char* dst = rg + lrow * PITCH + (((byte >> 4) ^ (lrow & (CPR - 1))) << 4) + (byte & 15);
+          if constexpr (EE == 2) {
+            uint2 w;
+            w.x = __builtin_bit_cast(uint32_t, __builtin_convertvector((float2v){v[0], v[1]}, bf16x2));
+            w.y = __builtin_bit_cast(uint32_t, __builtin_convertvector((float2v){v[2], v[3]}, bf16x2));
+            *reinterpret_cast<uint2*>(dst) = w;
+          } else {
+            const float4 o4 = *reinterpret_cast<const float4*>(pr + 2 * BN + n);
+            const float os[4] = {o4.x, o4.y, o4.z, o4.w};
+            uint32_t w = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) w |= (uint32_t)to_f8(v[q] * os[q]) << (8 * q);
+            *reinterpret_cast<uint32_t*>(dst) = w;
+          }
         }
       }
+    };
+    using F0 = std::false_type;
+    using F1 = std::true_type;
+    using E1 = std::integral_constant<int, 1>;
+    using E2 = std::integral_constant<int, 2>;
+    if (a.amax) {
+      if (E == 2) {
+        if (a.relu) convert(F1{}, E2{}, F1{});
+        else convert(F0{}, E2{}, F1{});
+      } else {
+        if (a.relu) convert(F1{}, E1{}, F1{});
+        else convert(F0{}, E1{}, F1{});
+      }
+    } else if (E == 2) {
+      if (a.relu) convert(F1{}, E2{}, F0{});
+      else convert(F0{}, E2{}, F0{});
+    } else {
+      if (a.relu) convert(F1{}, E1{}, F0{});
+      else convert(F0{}, E1{}, F0{});
     }
     // the wave reads back only its own region: its LDS operations complete
     // in order, so waiting for them is enough
@@ -305,21 +353,24 @@ void conv_resident(ConvArgs a, int n_tiles) {
     const int ty0 = (rem / tiles_x) * TH, tx0 = (rem % tiles_x) * TW;
     constexpr int CPR = BN * 4 / 16;  // 16-byte chunks per staged row
     float* region = reinterpret_cast<float*>(reinterpret_cast<char*>(&Ah[buf][0]) + wave * 32 * BN * 4);
+    const float* pr = params();
     __syncthreads();
 #pragma unroll
     for (int f = 0; f < FN; ++f) {
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
         const int n0 = f * 32 + 8 * g + 4 * lhalf;
+        const float4 b4 = *reinterpret_cast<const float4*>(pr + n0);
+        const float4 s4 = *reinterpret_cast<const float4*>(pr + BN + n0);
+        const float bq[4] = {b4.x, b4.y, b4.z, b4.w}, sq[4] = {s4.x, s4.y, s4.z, s4.w};
         float v[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int n = n0 + q;
-          const bool nok = n < a.n_rows;
-          const int o = nok ? (merged ? n % cout_m : n) : 0;
-          float x = acc[f][4 * g + q] * (a.w_scale ? a.w_scale[o] : 1.f) + a.bias[o];
+          float x = acc[f][4 * g + q] * sq[q] + bq[q];
           if (a.relu) x = fmaxf(x, 0.f);
-          if (a.amax && nok) atomicMax(reinterpret_cast<unsigned*>(a.amax) + o, __float_as_uint(fabsf(x)));
+          if (a.amax && n < a.n_rows)
+            atomicMax(reinterpret_cast<unsigned*>(a.amax) + (merged ? n % cout_m : n), __float_as_uint(fabsf(x)));
           v[q] = x;
         }
         *reinterpret_cast<float4*>(region + lrow * BN + (((n0 >> 2) ^ (lrow & (CPR - 1))) << 2)) =
@@ -386,8 +437,9 @@ void conv_resident(ConvArgs a, int n_tiles) {
         col = ((long)(ph >> 1) * a.Wout + (ph & 1)) * a.out_ld + o;
       }
       if (!n_ok) continue;
-      const float bn = a.bias[o];
-      const float ws = a.w_scale ? a.w_scale[o] : 1.f;
+      const float* pr = params();
+      const float bn = pr[n];
+      const float ws = pr[BN + n];
       float amax = 0.f;
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
