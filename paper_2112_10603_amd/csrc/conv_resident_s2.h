@@ -21,6 +21,8 @@
 // tap q / PC, PC = channels / 8.
 #pragma once
 
+#include <type_traits>
+
 #include "conv_resident.h"
 
 namespace ffv {
@@ -73,6 +75,8 @@ void conv_resident_s2(ConvArgs a, int n_tiles) {
   constexpr int KQ = 9 * PC;                // real K chunks
 
   __shared__ __attribute__((aligned(16))) uint4 smem[R::LDS_VECS];
+  // per output channel: bias, weight scale, fp8 output scale
+  __shared__ __attribute__((aligned(16))) float prm[3 * BN];
   uint4* Hb = smem;                         // two halo buffers
   uint4* Wl = smem + 2 * HV;                // resident weights
   char* St = reinterpret_cast<char*>(smem + 2 * HV + BN * RCP);  // output staging
@@ -82,6 +86,14 @@ void conv_resident_s2(ConvArgs a, int n_tiles) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lrow = lane & 31, lhalf = lane >> 5;
   const int pg = wave % PG, cg = wave / PG;
+  // the per-channel parameters, once per workgroup (published by the
+  // pipeline's first barrier)
+  for (int c = tid; c < BN; c += NT) {
+    const bool ok = c < a.n_rows;
+    prm[c] = ok ? a.bias[c] : 0.f;
+    prm[BN + c] = ok && a.w_scale ? a.w_scale[c] : 1.f;
+    prm[2 * BN + c] = ok && a.out_scale ? a.out_scale[c] : 1.f;
+  }
 
   const int G = gridDim.x, b = blockIdx.x;
   int t_first = b, t_step = G, t_end = n_tiles;
@@ -182,52 +194,79 @@ void conv_resident_s2(ConvArgs a, int n_tiles) {
   const int E = a.out_scale ? 1 : 2;
   const int pitch = WC * E, cpr = pitch / 16;
   char* region = St + wave * 32 * WC * 2;
-  auto epilogue = [&](int t) {
-    const int img = t / per_img, rem = t - img * per_img;
-    const int ty0 = (rem / tiles_x) * TH, tx0 = (rem % tiles_x) * TW;
+  // The conversion reads the parameters through an offset the compiler
+  // cannot see (an opaque zero), so they are re-read from LDS per block
+  // rather than held in registers across the block loop, and it is
+  // specialised on the uniform flags (ReLU, output type, calibration's
+  // running |max|) with no per-value branch.
+  auto convert = [&](auto relu_c, auto e_c, auto amax_c) {
+    constexpr bool RELU = decltype(relu_c)::value, AMAX = decltype(amax_c)::value;
+    constexpr int EE = decltype(e_c)::value;
+    constexpr int PITCH = WC * EE, CPR = PITCH / 16;
+    int z;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+    const float* pr = prm + z;
 #pragma unroll
     for (int f = 0; f < FN; ++f) {
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
         const int cw = f * 32 + 8 * g + 4 * lhalf;  // column within the wave's tile
         const int n = cg * WC + cw;
-        const bool nok = n < a.n_rows;
-        const int o = nok ? n : 0;
-        const float4 b4 = *reinterpret_cast<const float4*>(a.bias + o);
-        const float4 s4 = a.w_scale ? *reinterpret_cast<const float4*>(a.w_scale + o) : make_float4(1.f, 1.f, 1.f, 1.f);
+        const float4 b4 = *reinterpret_cast<const float4*>(pr + n);
+        const float4 s4 = *reinterpret_cast<const float4*>(pr + BN + n);
         const float bq[4] = {b4.x, b4.y, b4.z, b4.w}, sq[4] = {s4.x, s4.y, s4.z, s4.w};
-        float os[4] = {1.f, 1.f, 1.f, 1.f};
-        if (E == 1) {
-          const float4 o4 = *reinterpret_cast<const float4*>(a.out_scale + o);
-          os[0] = o4.x;
-          os[1] = o4.y;
-          os[2] = o4.z;
-          os[3] = o4.w;
-        }
         float v[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           float x = acc[f][4 * g + q] * sq[q] + bq[q];
-          if (a.relu) x = fmaxf(x, 0.f);
-          if (a.amax && nok) atomicMax(reinterpret_cast<unsigned*>(a.amax) + o + q, __float_as_uint(fabsf(x)));
+          if constexpr (RELU) x = fmaxf(x, 0.f);
           v[q] = x;
         }
-        const int byte = cw * E;
-        char* dst = region + lrow * pitch + (((byte >> 4) ^ (lrow & (cpr - 1))) << 4) + (byte & 15);
-        if (E == 2) {
+        if constexpr (AMAX) {
+          if (n < a.n_rows)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              atomicMax(reinterpret_cast<unsigned*>(a.amax) + n + q, __float_as_uint(fabsf(v[q])));
+        }
+        const int byte = cw * EE;
+        char* dst = region + lrow * PITCH + (((byte >> 4) ^ (lrow & (CPR - 1))) << 4) + (byte & 15);
+        if constexpr (EE == 2) {
           uint2 w;
-          w.x = (uint32_t)__builtin_bit_cast(uint16_t, (bf16)v[0]) |
-                ((uint32_t)__builtin_bit_cast(uint16_t, (bf16)v[1]) << 16);
-          w.y = (uint32_t)__builtin_bit_cast(uint16_t, (bf16)v[2]) |
-                ((uint32_t)__builtin_bit_cast(uint16_t, (bf16)v[3]) << 16);
+          w.x = __builtin_bit_cast(uint32_t, __builtin_convertvector((float2v){v[0], v[1]}, bf16x2));
+          w.y = __builtin_bit_cast(uint32_t, __builtin_convertvector((float2v){v[2], v[3]}, bf16x2));
           *reinterpret_cast<uint2*>(dst) = w;
         } else {
+          const float4 o4 = *reinterpret_cast<const float4*>(pr + 2 * BN + n);
+          const float os[4] = {o4.x, o4.y, o4.z, o4.w};
           uint32_t w = 0;
 #pragma unroll
           for (int q = 0; q < 4; ++q) w |= (uint32_t)to_f8(v[q] * os[q]) << (8 * q);
           *reinterpret_cast<uint32_t*>(dst) = w;
         }
       }
+    }
+  };
+  auto epilogue = [&](int t) {
+    const int img = t / per_img, rem = t - img * per_img;
+    const int ty0 = (rem / tiles_x) * TH, tx0 = (rem % tiles_x) * TW;
+    using F0 = std::false_type;
+    using F1 = std::true_type;
+    using E1 = std::integral_constant<int, 1>;
+    using E2 = std::integral_constant<int, 2>;
+    if (a.amax) {
+      if (E == 2) {
+        if (a.relu) convert(F1{}, E2{}, F1{});
+        else convert(F0{}, E2{}, F1{});
+      } else {
+        if (a.relu) convert(F1{}, E1{}, F1{});
+        else convert(F0{}, E1{}, F1{});
+      }
+    } else if (E == 2) {
+      if (a.relu) convert(F1{}, E2{}, F0{});
+      else convert(F0{}, E2{}, F0{});
+    } else {
+      if (a.relu) convert(F1{}, E1{}, F0{});
+      else convert(F0{}, E1{}, F0{});
     }
     __builtin_amdgcn_s_waitcnt(0xC07F);  // own region only: in-order LDS suffices
     __builtin_amdgcn_wave_barrier();
