@@ -226,14 +226,6 @@ void conv_resident(ConvArgs a, int n_tiles) {
   };
 
   // Epilogue of block t, whose last slice was computed from halo buffer buf.
-  // The epilogues read the parameters through an offset the compiler cannot
-  // see (an opaque zero), so it re-reads them from LDS per block instead of
-  // holding every column's values in registers across the block loop.
-  auto params = [&]() -> const float* {
-    int z;
-    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
-    return prm + z;
-  };
   // output pixel of GEMM grid point (oy, ox) when not phase-merged
   auto out_pix = [&](int oy, int ox) {
     return TAPS == 4 ? (long)(2 * oy + pyph) * a.Wout + 2 * ox + pxph : (long)oy * a.Wout + ox;
@@ -257,7 +249,7 @@ void conv_resident(ConvArgs a, int n_tiles) {
       constexpr int EE = decltype(e_c)::value;
       constexpr int PITCH = BN * EE, CPR = PITCH / 16;
       char* rg = reinterpret_cast<char*>(&Ah[buf][0]) + wave * 32 * PITCH;
-      const float* pr = params();
+      const float* pr = prm;
 #pragma unroll
       for (int f = 0; f < FN; ++f) {
 #pragma unroll
@@ -353,7 +345,7 @@ void conv_resident(ConvArgs a, int n_tiles) {
     const int ty0 = (rem / tiles_x) * TH, tx0 = (rem % tiles_x) * TW;
     constexpr int CPR = BN * 4 / 16;  // 16-byte chunks per staged row
     float* region = reinterpret_cast<float*>(reinterpret_cast<char*>(&Ah[buf][0]) + wave * 32 * BN * 4);
-    const float* pr = params();
+    const float* pr = prm;
     __syncthreads();
 #pragma unroll
     for (int f = 0; f < FN; ++f) {
@@ -437,7 +429,7 @@ void conv_resident(ConvArgs a, int n_tiles) {
         col = ((long)(ph >> 1) * a.Wout + (ph & 1)) * a.out_ld + o;
       }
       if (!n_ok) continue;
-      const float* pr = params();
+      const float* pr = prm;
       const float bn = pr[n];
       const float ws = pr[BN + n];
       float amax = 0.f;

@@ -194,18 +194,14 @@ void conv_resident_s2(ConvArgs a, int n_tiles) {
   const int E = a.out_scale ? 1 : 2;
   const int pitch = WC * E, cpr = pitch / 16;
   char* region = St + wave * 32 * WC * 2;
-  // The conversion reads the parameters through an offset the compiler
-  // cannot see (an opaque zero), so they are re-read from LDS per block
-  // rather than held in registers across the block loop, and it is
-  // specialised on the uniform flags (ReLU, output type, calibration's
-  // running |max|) with no per-value branch.
+  // The conversion reads the parameters from LDS and is specialised on the
+  // uniform flags (ReLU, output type, calibration's running |max|), with no
+  // per-value branch.
   auto convert = [&](auto relu_c, auto e_c, auto amax_c) {
     constexpr bool RELU = decltype(relu_c)::value, AMAX = decltype(amax_c)::value;
     constexpr int EE = decltype(e_c)::value;
     constexpr int PITCH = WC * EE, CPR = PITCH / 16;
-    int z;
-    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
-    const float* pr = prm + z;
+    const float* pr = prm;
 #pragma unroll
     for (int f = 0; f < FN; ++f) {
 #pragma unroll
