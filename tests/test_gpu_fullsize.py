@@ -67,3 +67,56 @@ def test_dense_1080p_batch_sampled_views(tmp_path):
         print(f"  max-abs {err:.3e}, PSNR {q:.2f} dB", flush=True)
         assert q >= 45.0
     net.close()
+
+
+# the FP8 bound (tests/test_gpu_fp8.py): PSNR_fp8 >= PSNR_bf16 - this, same input
+FP8_PSNR_DROP_DB = 27.09
+
+
+def test_fp8_4k_batch_sampled_view(tmp_path):
+    """FP8 at 4K in the benchmark's launch configuration: 4 pairs of
+    2160x3840 (disparity 0-96 px) at t = 1/2 in one call, the VIBlock convs
+    in FP8 e4m3 calibrated on a crop of a separately seeded 4K scene, tiles
+    autotuned in FP8. Pair 0's full 4K view against the FP64 oracle (FP8
+    within the derived bound of the BF16 path's PSNR on the same view, BF16
+    at >= 45 dB); graph replay, the view alone and the value range as
+    above."""
+    from paper_2112_10603_amd import Net
+    wfile = write_weights_file(str(tmp_path / "w0.ffvw"), seed=0)
+    pairs = [scenes.uhd_arc(2, seed=40 + i, device=DEV) for i in range(4)]
+    pv = [(p[0], p[1]) for p in pairs]
+    cal = scenes.uhd_arc(2, seed=99, device=DEV)
+    torch.cuda.synchronize()
+    print("case fp8 4k batch: calibrate and autotune", flush=True)
+    net = Net(wfile, "fp8", 0, workspace_bytes=64 << 30)
+    net.calibrate(cal[0, :, 1000:1256, 1800:2056].contiguous(), cal[1, :, 1000:1256, 1800:2056].contiguous(), 0.5)
+    del cal
+    out = torch.empty((4, 1, 3, 2160, 3840), dtype=torch.float32, device=DEV)
+    assert net.autotune(pv, [0.5], out) > 0
+    print("case fp8 4k batch: first call and graph replay", flush=True)
+    net.interpolate(pv, [0.5], out)
+    first = out.clone()
+    out.fill_(-1.0)
+    net.interpolate(pv, [0.5], out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, first)
+    del first
+    assert bool(torch.isfinite(out).all())
+    assert float(out.min()) >= 0.0 and float(out.max()) <= 1.0
+    print("case fp8 4k batch: pair 0 alone", flush=True)
+    alone = net.interpolate([pv[0]], [0.5])[0, 0]
+    assert torch.equal(alone, out[0, 0]), float((alone - out[0, 0]).abs().max())
+    got = out[0, 0].cpu().numpy()
+    del alone, out
+    net.close()
+    print("case fp8 4k batch: pair 0 in bf16", flush=True)
+    net16 = Net(wfile, "bf16", 0, workspace_bytes=16 << 30)
+    g16 = net16.interpolate([pv[0]], [0.5])[0, 0].cpu().numpy()
+    net16.close()
+    print("case fp8 4k batch: pair 0 oracle", flush=True)
+    ref = O.vinet_forward(pairs[0][0].cpu().numpy(), pairs[0][1].cpu().numpy(), 0.5, O.load_weights(wfile))
+    p8, p16 = psnr(got, ref), psnr(g16, ref)
+    print(f"  FP8 PSNR {p8:.2f} dB, max-abs {np.abs(got - ref).max():.3e}; "
+          f"BF16 PSNR {p16:.2f} dB, max-abs {np.abs(g16 - ref).max():.3e}", flush=True)
+    assert p16 >= 45.0
+    assert p8 >= p16 - FP8_PSNR_DROP_DB
