@@ -120,3 +120,46 @@ def test_fp8_4k_batch_sampled_view(tmp_path):
           f"BF16 PSNR {p16:.2f} dB, max-abs {np.abs(g16 - ref).max():.3e}", flush=True)
     assert p16 >= 45.0
     assert p8 >= p16 - FP8_PSNR_DROP_DB
+
+
+def test_serving_720p_1080p_mix_equals_alone(tmp_path):
+    """Serving in the benchmark's configuration (two 8-camera arcs at
+    1280x720 and 1920x1080 registered as resident cameras, 64 GB admission
+    budget, 5 ms tick, batches of up to 32 views): 24 requests of both sizes
+    queued at once, random adjacent pairs and phases, served twice (the
+    second time the batch's graph replays); every served view equals the
+    same view computed alone by ffv_interpolate, bit for bit."""
+    import time
+
+    from paper_2112_10603_amd import Net
+    wfile = write_weights_file(str(tmp_path / "w0.ffvw"), seed=0)
+    print("case serving 720p/1080p mix: register cameras", flush=True)
+    served = Net(wfile, "bf16", 0, hbm_budget_bytes=64 << 30, tick_ms=5.0, max_batch_views=32)
+    alone = Net(wfile, "bf16", 0, workspace_bytes=8 << 30)
+    arcs = {720: scenes.camera_arc(50, 720, 1280, 8, 1024, (8.0, 64.0), 48.0, 0.01, device=DEV),
+            1080: scenes.camera_arc(51, 1080, 1920, 8, 1024, (8.0, 64.0), 48.0, 0.01, device=DEV)}
+    for res, arc in arcs.items():
+        for j in range(8):
+            served.register_camera(res * 100 + j, arc[j].contiguous())
+    rng = np.random.default_rng(52)
+    reqs = []
+    for _ in range(24):
+        res = 720 if rng.random() < 0.5 else 1080
+        j = int(rng.integers(0, 7))
+        reqs.append((res, j, float(rng.uniform(0.0, 1.0))))
+    print("case serving 720p/1080p mix: views alone", flush=True)
+    refs = [alone.interpolate([(arcs[r][j], arcs[r][j + 1])], [t])[0, 0] for r, j, t in reqs]
+    alone.close()
+    for rnd in range(2):
+        print(f"case serving 720p/1080p mix: served round {rnd}", flush=True)
+        outs = [torch.full((3,) + tuple(arcs[r].shape[2:]), -1.0, device=DEV) for r, _, _ in reqs]
+        tickets = served.submit_many([(r * 100 + j, r * 100 + j + 1, t, o) for (r, j, t), o in zip(reqs, outs)])
+        pending, t0 = set(tickets), time.time()
+        while pending:
+            pending = {tk for tk in pending if served.poll(tk) is None}
+            assert time.time() - t0 < 120.0, f"{len(pending)} requests still pending"
+            time.sleep(0.002)
+        torch.cuda.synchronize()
+        for k, (o, ref) in enumerate(zip(outs, refs)):
+            assert torch.equal(o, ref), (rnd, k, reqs[k], float((o - ref).abs().max()))
+    served.close()
