@@ -251,3 +251,56 @@ def test_argument_errors(wfile):
     with pytest.raises(FfvError):
         net.interpolate([(x, x), (y, y)], [0.5])
     net.close()
+
+
+@pytest.mark.parametrize("H,W", [(2, 2), (2, 37), (19, 2), (16, 16)])
+def test_smallest_sizes_parity(wfile, oracle_w, H, W):
+    """The smallest images the boundary accepts (H, W >= 2; one 16 x 16
+    padded tile, the whole network at 4 x 4 pixels and below in its first
+    stage): FP32 within 1e-4 of the oracle, BF16 at >= 45 dB."""
+    print(f"case smallest size {H}x{W}", flush=True)
+    xl, xr = scenes.random_pair(31 + H + W, H, W, d_max=1.0)
+    ref = O.vinet_forward(xl.numpy(), xr.numpy(), 0.4, oracle_w)
+    for prec in ("fp32", "bf16"):
+        net = _net(wfile, prec)
+        out = net.interpolate([(xl.to(DEV), xr.to(DEV))], [0.4])[0, 0].cpu().numpy()
+        net.close()
+        assert out.shape == (3, H, W)
+        err = float(np.abs(out.astype(np.float64) - ref).max())
+        print(f"  {prec} max-abs {err:.3e}, PSNR {psnr(out, ref):.2f} dB", flush=True)
+        if prec == "fp32":
+            assert err <= 1e-4
+        else:
+            assert psnr(out, ref) >= 45.0
+
+
+def test_empty_and_degenerate_calls_through_abi(wfile):
+    """Empty batches, sizes below 2 or above the pixel limit, null pointers
+    and phases outside [0, 1] are refused with FFV_ERR_ARG before any
+    launch, and the net still works afterwards."""
+    import ctypes
+
+    from paper_2112_10603_amd import ffv
+    print("case empty and degenerate calls", flush=True)
+    net = _net(wfile)
+    L = ffv.lib()
+    x = torch.rand(3, 8, 8, device=DEV)
+    out = torch.empty(3, 8, 8, device=DEV)
+    ok = (ffv.ffv_pair * 1)(ffv.ffv_pair(x.data_ptr(), x.data_ptr(), 8, 8))
+    t = (ctypes.c_float * 1)(0.5)
+    h = net._h
+    assert L.ffv_interpolate(h, ok, 0, t, 1, out.data_ptr()) == -1
+    assert L.ffv_interpolate(h, ok, 1, t, 0, out.data_ptr()) == -1
+    assert L.ffv_interpolate(h, None, 1, t, 1, out.data_ptr()) == -1
+    assert L.ffv_interpolate(h, ok, 1, None, 1, out.data_ptr()) == -1
+    assert L.ffv_interpolate(h, ok, 1, t, 1, None) == -1
+    # sizes below 2, and one above the 2^28-pixel limit (refused before any allocation)
+    for hh, ww in ((1, 8), (8, 1), (0, 0), (-4, 8), (16385, 16385)):
+        bad = (ffv.ffv_pair * 1)(ffv.ffv_pair(x.data_ptr(), x.data_ptr(), hh, ww))
+        assert L.ffv_interpolate(h, bad, 1, t, 1, out.data_ptr()) == -1, (hh, ww)
+    for tv in (-0.01, 1.01, float("inf")):
+        tb = (ctypes.c_float * 1)(tv)
+        assert L.ffv_interpolate(h, ok, 1, tb, 1, out.data_ptr()) == -1, tv
+    got = net.interpolate([(x, x)], [0.5])[0, 0]
+    assert bool(torch.isfinite(got).all())
+    net.close()
