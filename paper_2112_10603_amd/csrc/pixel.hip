@@ -76,7 +76,24 @@ __device__ inline void pack_chunks(const float (&v)[N], uint4 (&c)[N * sizeof(T)
 // puts its record into the wave's LDS area (stage_put), the block meets at a
 // barrier, and each store instruction then writes 64 consecutive chunks
 // (stage_flush); records of pixels at or past the last valid one are not
-// written.
+// written. These stores, and the final pass's blended image, are marked
+// non-temporal: a pass streams out far more than the caches hold, so
+// keeping its output lines cached only evicts the camera rows and flow
+// taps its waves are still gathering (measured at 1080p x 112 views: final
+// pass 8.96 -> 8.38 ms, stage transitions 9.04 -> 8.71 ms, the kernels
+// that read the records unchanged).
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline void store_nt(uint4* dst, const uint4& w) {
+  const u32x4 v = {w.x, w.y, w.z, w.w};
+  __builtin_nontemporal_store(v, reinterpret_cast<u32x4*>(dst));
+}
+
+__device__ inline void store_nt(float* dst, const float4& w) {
+  const f32x4 v = {w.x, w.y, w.z, w.w};
+  __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(dst));
+}
+
 template <int NC>
 __device__ inline void stage_put(uint4* wave_stage, int lane, const uint4 (&c)[NC]) {
 #pragma unroll
@@ -88,7 +105,7 @@ __device__ inline void stage_flush(const uint4* wave_stage, int lane, uint4* dst
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
     const int c = k * 64 + lane;
-    if (c / NC < n_valid) dst[c] = wave_stage[c];
+    if (c / NC < n_valid) store_nt(dst + c, wave_stage[c]);
   }
 }
 
@@ -337,7 +354,7 @@ __global__ __launch_bounds__(TPB) void final_k(const ViewDesc* views, const CamD
   o.y = m * Wl.y + (1.f - m) * Wr.y;
   o.z = m * Wl.z + (1.f - m) * Wr.z;
   o.w = 0.f;
-  if (in) *reinterpret_cast<float4*>(I2 + ((long)v * P + p) * 4) = o;
+  if (in) store_nt(I2 + ((long)v * P + p) * 4, o);
   const float vals[24] = {L.x, L.y, L.z, R.x, R.y, R.z, Wl.x, Wl.y, Wl.z, Wr.x, Wr.y, Wr.z,
                           M, F.x, F.y, F.z, F.w, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   uint4 cx[NX];
